@@ -1,0 +1,250 @@
+"""Python binding of libllp, the MI355X (gfx950) LLP sweep.
+
+Argument marshalling only: every step of every solve runs in the HIP kernels
+of ``libllp.so`` behind the C ABI declared in ``include/llp.h``.  Torch is used
+for device memory (tensors) and streams.  There is no CPU fallback: importing
+works without the library, but every call raises ``LLPError`` when
+``libllp.so`` is missing or no GPU is present.
+
+Build the library with ``__graft_entry__.build()`` (or ``python -m
+paper_2603_13147_amd._build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libllp.so")
+
+INF32 = 2**31 - 1
+
+# status codes (llp_status)
+OK, E_ARG, E_INPUT, E_INFEASIBLE, E_OVERFLOW, E_NOT_CONVERGED, E_WORKSPACE, E_HIP, E_CYCLE, E_ABORTED = range(10)
+
+SCHED_PLAIN, SCHED_FIXED, SCHED_LEARNED, SCHED_HYBRID, SCHED_RANDOM = range(5)
+PUSH, DENSE, VALIDATE, ASYNC, VERIFY, TRACE, TIMING, JOBS_PULL = (1 << i for i in range(8))
+KIND_SSSP, KIND_BFS, KIND_SM, KIND_JOBS, KIND_KNAPSACK, KIND_TC, KIND_REDUCE, KIND_BATCH = range(1, 9)
+
+MLP_IN, MLP_HID, MLP_OUT = 12, 64, 5
+MLP_PARAMS = 64 * 12 + 64 + 64 * 64 + 64 + 5 * 64 + 5
+
+
+class LLPError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"llp status {status}: {msg}")
+        self.status = status
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int64), ("candidates", ctypes.c_int64),
+                ("edges_inspected", ctypes.c_int64), ("advances", ctypes.c_int64),
+                ("expand_edges", ctypes.c_int64), ("eval_launches", ctypes.c_int64),
+                ("device_ms", ctypes.c_float), ("kernel_ms", ctypes.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TraceRec(ctypes.Structure):
+    _fields_ = [("round", ctypes.c_int32), ("mode", ctypes.c_int32), ("in_count", ctypes.c_int32),
+                ("out_count", ctypes.c_int32), ("in_edges", ctypes.c_int64), ("out_edges", ctypes.c_int64),
+                ("bucket", ctypes.c_int32), ("pending", ctypes.c_int32)]
+
+
+TRACE_DTYPE = np.dtype([("round", np.int32), ("mode", np.int32), ("in_count", np.int32),
+                        ("out_count", np.int32), ("in_edges", np.int64), ("out_edges", np.int64),
+                        ("bucket", np.int32), ("pending", np.int32)])
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("sched", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("delta", ctypes.c_int32), ("max_rounds", ctypes.c_int64),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("stream", ctypes.c_void_p), ("warm_start", ctypes.c_void_p),
+                ("status_dev", ctypes.c_void_p), ("abort_host", ctypes.c_void_p),
+                ("stats", ctypes.POINTER(Stats)), ("chunk", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("trace_dev", ctypes.c_void_p), ("trace_cap", ctypes.c_int64), ("seed", ctypes.c_uint64)]
+
+
+class Graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64),
+                ("in_ptr", ctypes.c_void_p), ("in_src", ctypes.c_void_p), ("in_w", ctypes.c_void_p),
+                ("out_ptr", ctypes.c_void_p), ("out_dst", ctypes.c_void_p), ("out_w", ctypes.c_void_p)]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int32), ("cap_or_source", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("m", ctypes.c_int64), ("in_off", ctypes.c_int64),
+                ("out_off", ctypes.c_int64)]
+
+
+INSTANCE_DTYPE = np.dtype([("kind", np.int32), ("n", np.int32), ("cap_or_source", np.int32),
+                           ("pad", np.int32), ("m", np.int64), ("in_off", np.int64), ("out_off", np.int64)])
+
+_lib = None
+
+
+def lib():
+    """The loaded libllp.so (raises LLPError if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LLPError(E_HIP, f"{LIB_PATH} is missing: build the HIP library first")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    po = ctypes.POINTER(Opts)
+    L.llp_workspace_bytes.restype = sz
+    L.llp_workspace_bytes.argtypes = [ctypes.c_int, i64, i64, po]
+    L.llp_solve_sssp.argtypes = [ctypes.POINTER(Graph), i32, vp, po]
+    L.llp_solve_bfs.argtypes = [ctypes.POINTER(Graph), i32, vp, po]
+    L.llp_last_error.restype = ctypes.c_char_p
+    L.llp_version.restype = ctypes.c_char_p
+    L.llp_sched_set_weights.argtypes = [vp]
+    for name, args in [
+        ("llp_solve_sm", [i32, vp, vp, vp, vp, po]),
+        ("llp_solve_jobs", [i32, vp, vp, vp, vp, vp, vp, po]),
+        ("llp_solve_knapsack", [i32, i32, vp, vp, vp, vp, po]),
+        ("llp_solve_tc", [i32, i64, vp, vp, vp, po]),
+        ("llp_solve_reduce", [i64, vp, vp, po]),
+        ("llp_solve_batch", [i32, vp, vp, vp, vp, po]),
+        ("llp_solve_batch_graph", [i32, vp, vp, vp, vp, po]),
+        ("llp_autotune_batch", [i32, vp, vp, vp, ctypes.c_char_p, sz, po]),
+        ("llp_autotune_get", [ctypes.c_int, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        ("llp_mlp_forward", [i32, vp, vp, vp, vp, vp]),
+        ("llp_mlp_loss", [i32, vp, vp, vp, vp, vp]),
+        ("llp_mlp_backward", [i32, vp, vp, vp, vp, vp, vp]),
+        ("llp_mlp_adam", [vp, vp, vp, vp, i32, ctypes.c_float, vp]),
+        ("llp_trace_features", [i64, vp, i32, i64, vp, vp]),
+    ]:
+        if hasattr(L, name):
+            getattr(L, name).argtypes = args
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    """Names of the entry points libllp.so exports (checked against include/llp.h)."""
+    L = lib()
+    return L
+
+
+def _check(status):
+    if status != OK:
+        raise LLPError(status, lib().llp_last_error().decode(errors="replace"))
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise LLPError(E_HIP, "no GPU visible: libllp runs only on an MI355X (gfx950)")
+    return torch
+
+
+def _dev(t, dtype):
+    """Device tensor of the given torch dtype from a numpy array or tensor."""
+    torch = _torch()
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        t = torch.from_numpy(np.ascontiguousarray(t))
+    t = t.to(device="cuda", dtype=dtype)
+    return t.contiguous()
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_opts(sched=SCHED_PLAIN, flags=0, delta=0, max_rounds=0, workspace=None, stats=None, chunk=0,
+              block=0, trace=None, seed=0, warm_start=None, abort_host=None, status_dev=None):
+    o = Opts()
+    o.size = ctypes.sizeof(Opts)
+    o.sched = sched
+    o.flags = flags
+    o.delta = delta
+    o.max_rounds = max_rounds
+    if workspace is not None:
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    o.stream = _stream()
+    if warm_start is not None:
+        o.warm_start = warm_start.data_ptr()
+    if status_dev is not None:
+        o.status_dev = status_dev.data_ptr()
+    if abort_host is not None:
+        o.abort_host = abort_host.data_ptr()
+    if stats is not None:
+        o.stats = ctypes.pointer(stats)
+    o.chunk = chunk
+    o.block = block
+    if trace is not None:
+        o.trace_dev = trace.data_ptr()
+        o.trace_cap = trace.numel() // ctypes.sizeof(TraceRec)
+    o.seed = seed
+    return o
+
+
+def workspace(kind, n, m):
+    torch = _torch()
+    nbytes = int(lib().llp_workspace_bytes(kind, n, m, None))
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device="cuda")
+
+
+# ---------------------------------------------------------------- graphs
+class DeviceGraph:
+    """Device copy of a CSRGraph-like object (in_ptr/in_src/in_w, out_ptr/out_dst/out_w)."""
+
+    def __init__(self, csr, weighted=True):
+        torch = _torch()
+        i32 = torch.int32
+        self.n, self.m = int(csr.n), int(csr.m)
+        self.in_ptr = _dev(csr.in_ptr, i32)
+        self.in_src = _dev(csr.in_src, i32)
+        self.in_w = _dev(csr.in_w, i32) if (weighted and csr.in_w is not None) else None
+        self.out_ptr = _dev(csr.out_ptr, i32)
+        self.out_dst = _dev(csr.out_dst, i32)
+        ow = getattr(csr, "out_w", None)
+        self.out_w = _dev(ow, i32) if (weighted and ow is not None) else None
+
+    def cstruct(self):
+        g = Graph()
+        g.n, g.m = self.n, self.m
+        g.in_ptr, g.in_src, g.in_w = (t.data_ptr() if t is not None else None
+                                      for t in (self.in_ptr, self.in_src, self.in_w))
+        g.out_ptr, g.out_dst, g.out_w = (t.data_ptr() if t is not None else None
+                                         for t in (self.out_ptr, self.out_dst, self.out_w))
+        return g
+
+
+def _graph_solve(fn, kind, dg, source, out, opts):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(dg.n, dtype=torch.int32, device="cuda")
+    g = dg.cstruct()
+    _check(fn(ctypes.byref(g), int(source), _ptr(out), ctypes.byref(opts)))
+    return out
+
+
+def sssp(dg, source, out=None, ws=None, **kw):
+    """Shortest distances from `source` (int32 tensor; 2**31-1 = unreachable)."""
+    if ws is None:
+        ws = workspace(KIND_SSSP, dg.n, dg.m)
+    o = make_opts(workspace=ws, **kw)
+    return _graph_solve(lib().llp_solve_sssp, KIND_SSSP, dg, source, out, o)
+
+
+def bfs(dg, source, out=None, ws=None, **kw):
+    """Breadth-first levels from `source` (int32 tensor; 2**31-1 = unreachable)."""
+    if ws is None:
+        ws = workspace(KIND_BFS, dg.n, dg.m)
+    o = make_opts(workspace=ws, **kw)
+    return _graph_solve(lib().llp_solve_bfs, KIND_BFS, dg, source, out, o)

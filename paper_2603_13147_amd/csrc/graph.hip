@@ -1,0 +1,581 @@
+// graph.hip - the LLP sweep for single-source shortest paths (paper Section
+// 5.2) and breadth-first search (Section 5.3) on gfx950.
+//
+// State.  G[v] = INF - d(v) with INF = 2^31 - 1, so the bottom of the lattice
+// is G = 0 (d = infinity) and every advance is an int32 atomicMax.  The
+// paper's predicate "v is forbidden iff d(v) > d(u) + w(u, v) for an in-arc"
+// becomes "G[v] < G[u] - w(u, v) for an in-arc with G[u] > 0", and alpha(G, v)
+// is the largest such G[u] - w (Definition 3).  The source has alpha = INF.
+// Any partial maximum over a subset of in-arcs is also an alpha-forbidden
+// advance, which is what lets a hub's in-arcs be split across waves and the
+// push rounds advance one arc at a time.
+//
+// Rounds.  Each round is enqueued as two kernels (PRE, MAIN); the kernel
+// boundary is the grid-wide synchronisation (on gfx950 a device-side grid
+// barrier, whose agent-scope fences flush and invalidate every XCD's L2 per
+// wave, costs far more than a launch).  PRE reads the changed list CL[r-1],
+// decides the round's mode, and either expands CL[r-1] into the candidate
+// worklist WL (successor expansion, Section 4.2) or pushes along its
+// out-arcs.  MAIN evaluates the candidates (or every vertex in a dense round)
+// and produces CL[r].  A round whose input list is empty sets the device
+// `done` flag; later kernels return at once.  The host polls the flag every
+// few rounds.
+#include <string.h>
+
+#include <vector>
+
+#include "llp_host.h"
+#include "llp_lists.h"
+#include "llp_sched.h"
+
+namespace llp {
+
+constexpr int GB = 512;            // threads per workgroup
+constexpr int GW = GB / LLP_WAVE;  // waves per workgroup
+constexpr int MAX_SEG = 2048;      // max workgroups per phase kernel
+
+enum { MODE_PULL = 0, MODE_DENSE = 1, MODE_PUSH = 2 };
+
+struct GCtrl {
+    int done;
+    int status;
+    int last_round;
+    int mode;
+    int ovf;
+    int verify_changed;
+    int pad0, pad1;
+    int diag[8];        // first guard event: site, index, bound, context
+    long long rounds, cand, edges, adv, xedges;
+    SchedHist hist[2];  // scheduler history, double-buffered by round parity
+};
+
+struct GArgs {
+    int n, m;
+    const int* in_ptr;
+    const int* in_src;
+    const int* in_w;
+    const int* out_ptr;
+    const int* out_dst;
+    const int* out_w;
+    int* G;
+    int* stamp;
+    int* cstamp;
+    ListRef wl, cl0, cl1;
+    int nseg;
+    int source;
+    int unit_w;        // BFS: every weight is 1
+    int warm_dense;    // warm start: round 1 is dense
+    GCtrl* ctrl;
+    llp_trace_rec* trace;
+    long long trace_cap;
+    SchedParams sp;
+};
+
+__device__ __forceinline__ ListRef cl_of(const GArgs& a, int r) { return (r & 1) ? a.cl1 : a.cl0; }
+
+// --------------------------------------------------------------- init
+__global__ void k_graph_init(GArgs a, const int* warm) {
+    const long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long nt = (long long)gridDim.x * blockDim.x;
+    for (long long v = tid; v < a.n; v += nt) {
+        int g = 0;
+        if (warm) {
+            int d = warm[v];
+            g = (d >= LLP_INF || d < 0) ? 0 : LLP_INF - d;
+        }
+        if (v == a.source) g = LLP_INF;
+        a.G[v] = g;
+        a.stamp[v] = 0;
+        a.cstamp[v] = 0;
+    }
+    for (long long s = tid; s < a.nseg; s += nt) {
+        a.cl0.seg[s] = 0ull;
+        a.cl1.seg[s] = 0ull;
+        a.wl.seg[s] = 0ull;
+    }
+    if (tid == 0) {
+        GCtrl c;
+        memset(&c, 0, sizeof(c));
+        c.mode = -1;
+        *a.ctrl = c;
+        // CL[0] = {source}: one entry in segment 0
+        int ob = a.out_ptr ? a.out_ptr[a.source] : 0;
+        int od = a.out_ptr ? a.out_ptr[a.source + 1] - ob : 0;
+        if (od > 0) {
+            a.cl0.ent[0] = make_int4(a.source, ob, 0, od);
+            a.cl0.seg[0] = 1ull | ((unsigned long long)(unsigned)od << 32);
+        }
+    }
+}
+
+// --------------------------------------------------------------- validation
+__global__ void k_graph_validate(GArgs a) {
+    const long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long nt = (long long)gridDim.x * blockDim.x;
+    int bad = 0;
+    for (long long v = tid; v <= a.n; v += nt) {
+        int p = a.in_ptr[v];
+        if (v == 0 && p != 0) bad = 1;
+        if (v == a.n && p != a.m) bad = 1;
+        if (v < a.n && a.in_ptr[v + 1] < p) bad = 1;
+        if (a.out_ptr) {
+            int q = a.out_ptr[v];
+            if (v == 0 && q != 0) bad = 1;
+            if (v == a.n && q != a.m) bad = 1;
+            if (v < a.n && a.out_ptr[v + 1] < q) bad = 1;
+        }
+    }
+    for (long long e = tid; e < a.m; e += nt) {
+        int u = a.in_src[e];
+        if (u < 0 || u >= a.n) bad = 1;
+        if (!a.unit_w && a.in_w && a.in_w[e] < 0) bad = 1;
+        if (a.out_dst) {
+            int x = a.out_dst[e];
+            if (x < 0 || x >= a.n) bad = 1;
+        }
+        if (!a.unit_w && a.out_w && a.out_w[e] < 0) bad = 1;
+    }
+    if (bad) set_status(&a.ctrl->status, LLP_E_INPUT);
+}
+
+// --------------------------------------------------------------- helpers
+struct GShared {
+    int cnt[MAX_SEG];
+    int epre[MAX_SEG + 1];
+    int own[GW][64];
+    unsigned long long ctr;
+    int tot_edges, tot_count;
+    int mode;
+    int tmp[GW + 1];
+};
+
+// Candidate value pulled through arc (u -> v) of weight w: G[u] - w when u is
+// reached and the result stays a reached value; flags overflow otherwise.
+__device__ __forceinline__ int pull_cand(int gu, int w, bool& ovf) {
+    if (gu <= 0) return 0;
+    int c = gu - w;
+    if (c <= 0) { ovf = true; return 0; }
+    return c;
+}
+
+// Evaluate edges of the iteration: segmented max of candidates per owner,
+// advance owners by atomicMax, append changed vertices to CL.
+__device__ __forceinline__ void eval_body(const GArgs& a, const EdgeCtx& c, int r, const ListRef& out,
+                                          GShared& sh, bool& ovf, long long& nadv) {
+    const int l = lane();
+    int cand = 0;
+    if (c.active) {
+        int e = guard(c.csr, a.m, a.ctrl->diag, 41, c.own.y, c.own.z);
+        int u = guard(a.in_src[e], a.n, a.ctrl->diag, 42, e, 0);
+        int w = a.unit_w ? 1 : a.in_w[e];
+        cand = pull_cand(a.G[u], w, ovf);
+    }
+    int seg = c.active ? c.j : 64 + l;
+    int x = seg_incl_max(cand, seg);
+    int nseg = __shfl_down(seg, 1, LLP_WAVE);
+    bool tail = c.active && (l == 63 || nseg != seg);
+    bool changed = false;
+    int v = guard(c.own.x, a.n, a.ctrl->diag, 43, c.j, c.own.z);
+    if (tail && x > 0) {
+        int gv = a.G[v];
+        if (x > gv) {
+            int old = amax(&a.G[v], x);
+            if (old < x) changed = (amax(&a.cstamp[v], r) < r);
+        }
+    }
+    int ob = 0, od = 0;
+    if (changed) {
+        ob = a.out_ptr[v];
+        od = a.out_ptr[v + 1] - ob;
+        nadv++;
+    }
+    append(changed && od > 0, v, ob, od, &sh.ctr, out, &a.ctrl->status);
+}
+
+// Expansion: stamp out-neighbours for round r and append new candidates to WL.
+__device__ __forceinline__ void expand_body(const GArgs& a, const EdgeCtx& c, int r, GShared& sh) {
+    bool fresh = false;
+    int x = 0, rb = 0, d = 0;
+    if (c.active) {
+        x = guard(a.out_dst[guard(c.csr, a.m, a.ctrl->diag, 51, c.own.y, c.own.z)], a.n, a.ctrl->diag, 52);
+        if (a.stamp[x] < r && amax(&a.stamp[x], r) < r) {
+            rb = a.in_ptr[x];
+            d = a.in_ptr[x + 1] - rb;
+            fresh = d > 0;
+        }
+    }
+    append(fresh, x, rb, d, &sh.ctr, a.wl, &a.ctrl->status);
+}
+
+// Push: single-arc partial advance of each out-neighbour (Definition 3).
+__device__ __forceinline__ void push_body(const GArgs& a, const EdgeCtx& c, int r, const ListRef& out,
+                                          GShared& sh, bool& ovf, long long& nadv) {
+    int gmine = c.mine_valid ? a.G[guard(c.mine.x, a.n, a.ctrl->diag, 61)] : 0;
+    int gu = shfl(gmine, c.j);
+    bool changed = false;
+    int x = 0, ob = 0, od = 0;
+    if (c.active) {
+        int e = guard(c.csr, a.m, a.ctrl->diag, 62, c.own.y, c.own.z);
+        x = guard(a.out_dst[e], a.n, a.ctrl->diag, 63);
+        int w = a.unit_w ? 1 : a.out_w[e];
+        int cand = pull_cand(gu, w, ovf);
+        if (cand > 0 && cand > a.G[x]) {
+            int old = amax(&a.G[x], cand);
+            if (old < cand) changed = (amax(&a.cstamp[x], r) < r);
+        }
+    }
+    if (changed) {
+        ob = a.out_ptr[x];
+        od = a.out_ptr[x + 1] - ob;
+        nadv++;
+    }
+    append(changed && od > 0, x, ob, od, &sh.ctr, out, &a.ctrl->status);
+}
+
+__device__ __forceinline__ void wave_range(int total, int& wb, int& we) {
+    const long long W = (long long)gridDim.x * GW;
+    const long long w = (long long)blockIdx.x * GW + (threadIdx.x >> 6);
+    wb = (int)((long long)total * w / W);
+    we = (int)((long long)total * (w + 1) / W);
+}
+
+__device__ __forceinline__ void finish_segment(GShared& sh, const ListRef& out) {
+    __syncthreads();
+    if (threadIdx.x == 0) out.seg[blockIdx.x] = sh.ctr;
+}
+
+// --------------------------------------------------------------- PRE
+__global__ void __launch_bounds__(GB) k_graph_pre(GArgs a, int r) {
+    __shared__ GShared sh;
+    if (ld_relaxed(&a.ctrl->done) || ld_relaxed(&a.ctrl->status)) return;
+    const ListRef in = cl_of(a, r - 1);
+    const ListRef out = cl_of(a, r);
+    load_segments(in.seg, a.nseg, sh.cnt, sh.epre, sh.tmp, &sh.tot_edges, &sh.tot_count);
+    const int force_dense = (r == 1 && a.warm_dense);
+    if (sh.tot_count == 0 && !force_dense) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            a.ctrl->done = 1;
+            a.ctrl->last_round = r - 1;
+        }
+        return;
+    }
+    // schedule decision (identical in every workgroup)
+    if (threadIdx.x < 64) {
+        int mode = decide_mode(a.sp, a.ctrl->hist[(r + 1) & 1], r, sh.tot_count, sh.tot_edges, a.n, a.m,
+                               force_dense);
+        if (threadIdx.x == 0) sh.mode = mode;
+    }
+    if (threadIdx.x == 0) sh.ctr = 0ull;
+    __syncthreads();
+    const int mode = sh.mode;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        GCtrl* c = a.ctrl;
+        c->mode = mode;
+        c->rounds = r;
+        c->adv += sh.tot_count;
+        if (mode == MODE_PULL) c->xedges += sh.tot_edges;
+        if (mode == MODE_PUSH) {
+            c->edges += sh.tot_edges;
+            c->cand += sh.tot_count;
+        }
+        hist_push(c->hist[r & 1], c->hist[(r + 1) & 1], r, mode, sh.tot_count, sh.tot_edges);
+        if (a.trace && r - 1 < a.trace_cap) {
+            llp_trace_rec t;
+            t.round = r;
+            t.mode = mode;
+            t.in_count = sh.tot_count;
+            t.out_count = 0;
+            t.in_edges = sh.tot_edges;
+            t.out_edges = 0;
+            t.bucket = -1;
+            t.pending = 0;
+            a.trace[r - 1] = t;
+        }
+    }
+    if (mode == MODE_DENSE) return;
+    SegView sv{in.ent, in.cap, a.nseg, sh.cnt, sh.epre, sh.tot_edges, sh.tot_count};
+    ListSrc src{sv, a.ctrl->diag};
+    int wb, we;
+    wave_range(sh.tot_edges, wb, we);
+    int* own = sh.own[threadIdx.x >> 6];
+    bool ovf = false;
+    long long nadv = 0;
+    if (mode == MODE_PULL) {
+        for_edges(src, wb, we, own, [&](const EdgeCtx& c) { expand_body(a, c, r, sh); });
+        finish_segment(sh, a.wl);
+    } else {
+        for_edges(src, wb, we, own, [&](const EdgeCtx& c) { push_body(a, c, r, out, sh, ovf, nadv); });
+        finish_segment(sh, out);
+    }
+    if (__any(ovf) && lane() == 0) st_relaxed(&a.ctrl->ovf, 1);
+}
+
+// --------------------------------------------------------------- MAIN
+// verify != 0: a dense round on the final state that must change nothing.
+__global__ void __launch_bounds__(GB) k_graph_main(GArgs a, int r, int verify) {
+    __shared__ GShared sh;
+    if (!verify && (ld_relaxed(&a.ctrl->done) || ld_relaxed(&a.ctrl->status))) return;
+    const int mode = verify ? MODE_DENSE : a.ctrl->mode;
+    if (mode == MODE_PUSH) return;
+    const ListRef out = verify ? a.wl : cl_of(a, r);   // verify writes into WL's storage
+    if (threadIdx.x == 0) sh.ctr = 0ull;
+    int* own = sh.own[threadIdx.x >> 6];
+    bool ovf = false;
+    long long nadv = 0;
+    int wb, we;
+    if (mode == MODE_DENSE) {
+        __syncthreads();
+        if (blockIdx.x == 0 && threadIdx.x == 0 && !verify) {
+            a.ctrl->cand += a.n;
+            a.ctrl->edges += a.m;
+        }
+        DenseSrc src{a.in_ptr, a.n, a.ctrl->diag};
+        wave_range(a.m, wb, we);
+        int rr = verify ? r + 1 : r;
+        for_edges(src, wb, we, own, [&](const EdgeCtx& c) { eval_body(a, c, rr, out, sh, ovf, nadv); });
+    } else {
+        load_segments(a.wl.seg, a.nseg, sh.cnt, sh.epre, sh.tmp, &sh.tot_edges, &sh.tot_count);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            a.ctrl->cand += sh.tot_count;
+            a.ctrl->edges += sh.tot_edges;
+            a.ctrl->hist[r & 1].wl_count = sh.tot_count;
+            a.ctrl->hist[r & 1].wl_edges = sh.tot_edges;
+        }
+        SegView sv{a.wl.ent, a.wl.cap, a.nseg, sh.cnt, sh.epre, sh.tot_edges, sh.tot_count};
+        ListSrc src{sv, a.ctrl->diag};
+        wave_range(sh.tot_edges, wb, we);
+        for_edges(src, wb, we, own, [&](const EdgeCtx& c) { eval_body(a, c, r, out, sh, ovf, nadv); });
+    }
+    finish_segment(sh, out);
+    if (__any(ovf) && lane() == 0) st_relaxed(&a.ctrl->ovf, 1);
+    if (verify) {
+        long long tot = wave_sum64(nadv);
+        if (lane() == 0 && tot) st_relaxed(&a.ctrl->verify_changed, 1);
+    }
+}
+
+// --------------------------------------------------------------- finish
+// Overflow: a vertex still at the bottom with a reached in-neighbour has a
+// true distance >= INF.  Only run when a candidate overflowed.
+__global__ void k_graph_ovf(GArgs a) {
+    if (!ld_relaxed(&a.ctrl->ovf)) return;
+    const long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long nt = (long long)gridDim.x * blockDim.x;
+    for (long long v = tid; v < a.n; v += nt) {
+        if (a.G[v] != 0) continue;
+        bool bad = false;
+        for (int e = a.in_ptr[v]; e < a.in_ptr[v + 1]; ++e)
+            if (a.G[clampi(a.in_src[clampi(e, a.m, bad)], a.n, bad)] > 0) {
+                set_status(&a.ctrl->status, LLP_E_OVERFLOW);
+                break;
+            }
+    }
+}
+
+// In place: G -> distance (INF for unreached).
+__global__ void k_graph_decode(int* G, int n) {
+    const long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long nt = (long long)gridDim.x * blockDim.x;
+    for (long long v = tid; v < n; v += nt) {
+        int g = G[v];
+        G[v] = g > 0 ? LLP_INF - g : LLP_INF;
+    }
+}
+
+// --------------------------------------------------------------- host
+struct GraphLayout {
+    int nseg;
+    int cap;
+};
+
+static GraphLayout graph_layout(int64_t m) {
+    const DeviceInfo& d = device_info();
+    GraphLayout L;
+    L.nseg = d.cus * 4;
+    if (L.nseg > MAX_SEG) L.nseg = MAX_SEG;
+    long long W = (long long)L.nseg * GW;
+    long long per_wave = (m + W - 1) / W;
+    L.cap = (int)(GW * per_wave + GW * 2 + 64);
+    return L;
+}
+
+static size_t graph_ws(int64_t n, int64_t m, GArgs* a, char* base, size_t cap) {
+    GraphLayout L = graph_layout(m);
+    Carver cv{base, cap, 0, base == nullptr};
+    int* stamp = cv.take<int>(n);
+    int* cstamp = cv.take<int>(n);
+    GCtrl* ctrl = cv.take<GCtrl>(1);
+    ListRef lists[3];
+    for (int i = 0; i < 3; ++i) {
+        lists[i].seg = cv.take<unsigned long long>(L.nseg);
+        lists[i].ent = cv.take<int4>((size_t)L.nseg * L.cap);
+        lists[i].cap = L.cap;
+    }
+    if (a) {
+        a->stamp = stamp;
+        a->cstamp = cstamp;
+        a->ctrl = ctrl;
+        a->wl = lists[0];
+        a->cl0 = lists[1];
+        a->cl1 = lists[2];
+        a->nseg = L.nseg;
+    }
+    return cv.used;
+}
+
+size_t graph_workspace_bytes(int64_t n, int64_t m) { return graph_ws(n, m, nullptr, nullptr, 0); }
+
+static int launch_grid_1d(int64_t work) {
+    int64_t g = (work + 255) / 256;
+    if (g < 1) g = 1;
+    int cap = device_info().cus * 8;
+    return (int)(g < cap ? g : cap);
+}
+
+int solve_graph(const llp_graph* g, int32_t source, int32_t* out, const llp_opts* opts, bool bfs) {
+    if (!g) return fail(LLP_E_ARG, "graph is NULL");
+    if (!out) return fail(LLP_E_ARG, "output is NULL");
+    if (g->n <= 0) return fail(LLP_E_ARG, "n must be positive (got %d)", g->n);
+    if (g->m < 0 || g->m > (int64_t)0x7fffffff - (1 << 20)) return fail(LLP_E_ARG, "m out of range");
+    if (source < 0 || source >= g->n) return fail(LLP_E_ARG, "source %d out of range [0, %d)", source, g->n);
+    if (!g->in_ptr || (g->m > 0 && !g->in_src)) return fail(LLP_E_ARG, "in-CSR arrays are required");
+    if (!bfs && g->m > 0 && !g->in_w) return fail(LLP_E_ARG, "SSSP needs in_w (use llp_solve_bfs for unit weights)");
+    llp_opts o = opts_or_default(opts);
+    hipStream_t st = (hipStream_t)o.stream;
+    const bool need_out = true;
+    if (need_out && (!g->out_ptr || (g->m > 0 && !g->out_dst)))
+        return fail(LLP_E_ARG, "out-CSR (out_ptr, out_dst) is required for successor expansion");
+    if (o.sched == LLP_SCHED_FIXED && (o.flags & LLP_PUSH) && !bfs && !g->out_w)
+        return fail(LLP_E_ARG, "push rounds need out_w");
+    if (o.sched > LLP_SCHED_RANDOM) return fail(LLP_E_ARG, "unknown schedule %u", o.sched);
+
+    GArgs a;
+    memset(&a, 0, sizeof(a));
+    a.n = g->n;
+    a.m = (int)g->m;
+    a.in_ptr = g->in_ptr;
+    a.in_src = g->in_src;
+    a.in_w = bfs ? nullptr : g->in_w;
+    a.out_ptr = g->out_ptr;
+    a.out_dst = g->out_dst;
+    a.out_w = bfs ? nullptr : g->out_w;
+    a.G = out;
+    a.source = source;
+    a.unit_w = bfs ? 1 : 0;
+    a.trace = (o.flags & LLP_TRACE) ? o.trace_dev : nullptr;
+    a.trace_cap = o.trace_cap;
+    a.warm_dense = o.warm_start ? 1 : 0;
+    int s = sched_params(o, bfs || g->out_w != nullptr, &a.sp);
+    if (s) return s;
+
+    size_t need = graph_ws(g->n, g->m, nullptr, nullptr, 0);
+    void* ws = nullptr;
+    s = get_workspace(o, need, &ws);
+    if (s) return s;
+    graph_ws(g->n, g->m, &a, (char*)ws, need);
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    const bool timing = (o.flags & LLP_TIMING) && o.stats;
+    if (timing) {
+        LLP_HIP(hipEventCreate(&ev0));
+        LLP_HIP(hipEventCreate(&ev1));
+        LLP_HIP(hipEventRecord(ev0, st));
+    }
+    const int g1 = launch_grid_1d(g->n > g->m ? g->n : g->m);
+    hipLaunchKernelGGL(k_graph_init, dim3(launch_grid_1d(g->n)), dim3(256), 0, st, a, o.warm_start);
+    if (o.flags & LLP_VALIDATE) hipLaunchKernelGGL(k_graph_validate, dim3(g1), dim3(256), 0, st, a);
+    LLP_HIP(hipGetLastError());
+
+    const int64_t max_rounds = o.max_rounds > 0 ? o.max_rounds : (int64_t)g->n + 2;
+    GCtrl h;
+    memset(&h, 0, sizeof(h));
+    int64_t r = 1;
+    int batch = 4;
+    int status = LLP_OK;
+    std::vector<hipEvent_t> evs;     // LLP_TIMING: one pair around each MAIN launch
+    for (;;) {
+        for (int i = 0; i < batch && r <= max_rounds; ++i, ++r) {
+            hipLaunchKernelGGL(k_graph_pre, dim3(a.nseg), dim3(GB), 0, st, a, (int)r);
+            if (timing) {
+                hipEvent_t e0, e1;
+                LLP_HIP(hipEventCreate(&e0));
+                LLP_HIP(hipEventCreate(&e1));
+                LLP_HIP(hipEventRecord(e0, st));
+                hipLaunchKernelGGL(k_graph_main, dim3(a.nseg), dim3(GB), 0, st, a, (int)r, 0);
+                LLP_HIP(hipEventRecord(e1, st));
+                evs.push_back(e0);
+                evs.push_back(e1);
+            } else {
+                hipLaunchKernelGGL(k_graph_main, dim3(a.nseg), dim3(GB), 0, st, a, (int)r, 0);
+            }
+        }
+        LLP_HIP(hipGetLastError());
+        s = readback(st, a.ctrl, &h, sizeof(h));
+        if (s) return s;
+        if (h.status) break;
+        if (h.done) break;
+        if (o.abort_host && *o.abort_host) { status = LLP_E_ABORTED; break; }
+        if (r > max_rounds) { status = LLP_E_NOT_CONVERGED; break; }
+        if (batch < 16) batch *= 2;
+    }
+    if (status == LLP_OK && h.status == 0 && (o.flags & LLP_VERIFY)) {
+        hipLaunchKernelGGL(k_graph_main, dim3(a.nseg), dim3(GB), 0, st, a, (int)h.last_round + 1, 1);
+    }
+    if (h.status == 0) hipLaunchKernelGGL(k_graph_ovf, dim3(g1), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_graph_decode, dim3(launch_grid_1d(g->n)), dim3(256), 0, st, out, g->n);
+    LLP_HIP(hipGetLastError());
+    if (timing) LLP_HIP(hipEventRecord(ev1, st));
+    s = readback(st, a.ctrl, &h, sizeof(h));
+    if (s) return s;
+    if (o.stats) {
+        o.stats->rounds = h.rounds;
+        o.stats->candidates = h.cand;
+        o.stats->edges_inspected = h.edges;
+        o.stats->advances = h.adv;
+        o.stats->expand_edges = h.xedges;
+        o.stats->eval_launches = (int64_t)(evs.size() / 2);
+        if (timing) {
+            float ms = 0.f, kms = 0.f;
+            LLP_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+            for (size_t i = 0; i + 1 < evs.size(); i += 2) {
+                float t = 0.f;
+                LLP_HIP(hipEventElapsedTime(&t, evs[i], evs[i + 1]));
+                kms += t;
+            }
+            o.stats->device_ms = ms;
+            o.stats->kernel_ms = kms;
+        }
+    }
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    if (timing) {
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+    }
+    if (h.diag[0]) {
+        return fail(LLP_E_INPUT, "index guard %d fired: index %d bound %d context %d %d (round %lld)", h.diag[0],
+                    h.diag[1], h.diag[2], h.diag[3], h.diag[4], h.rounds);
+    }
+    if (h.status) {
+        if (h.status == LLP_E_INPUT) return fail(LLP_E_INPUT, "device validation rejected the graph");
+        if (h.status == LLP_E_OVERFLOW) return fail(LLP_E_OVERFLOW, "a reachable distance does not fit int32");
+        return fail(h.status, "device status %d", h.status);
+    }
+    if (h.verify_changed) return fail(LLP_E_HIP, "verification round advanced an index after convergence");
+    if (status == LLP_E_NOT_CONVERGED) return fail(status, "not converged after %lld rounds", (long long)max_rounds);
+    if (status == LLP_E_ABORTED) return fail(status, "aborted by the host flag");
+    return LLP_OK;
+}
+
+}  // namespace llp
+
+extern "C" {
+
+int llp_solve_sssp(const llp_graph* g, int32_t source, int32_t* dist, const llp_opts* opts) {
+    return llp::solve_graph(g, source, dist, opts, false);
+}
+
+int llp_solve_bfs(const llp_graph* g, int32_t source, int32_t* level, const llp_opts* opts) {
+    return llp::solve_graph(g, source, level, opts, true);
+}
+
+}  // extern "C"

@@ -1,0 +1,148 @@
+// llp_sched.h - per-round schedule choice of the graph sweep.
+//
+// The paper leaves the choice of solver (all-indices, worklist, buckets) to
+// the user per workload and names a runtime monitor that samples the
+// frontier and switches policy as future work (Section 6, Section 7).  Every
+// choice here is only a schedule: the least fixpoint is the same whatever
+// the mode of each round.  Modes: pull over the compacted candidate
+// worklist, dense pull over every index, push along out-arcs.
+//
+// LLP_SCHED_LEARNED runs a 12 -> 64 -> 64 -> 5 MLP (bf16 weights, fp32
+// accumulation) on 12 frontier features in one wave of every workgroup; all
+// workgroups compute bit-identical inputs and therefore the same decision.
+#pragma once
+
+#include "llp_dev.h"
+#include "../../include/llp.h"
+
+namespace llp {
+
+struct SchedHist {
+    int r;               // round that wrote this record
+    int mode;            // mode of that round
+    int cl_count;        // changed indices that round consumed (input list)
+    int cl_edges;
+    int wl_count;        // candidates it evaluated (pull rounds)
+    int wl_edges;
+    int pad0, pad1;
+    long long adv_total; // cumulative changed indices
+};
+
+struct SchedParams {
+    unsigned sched;
+    unsigned flags;
+    int delta;
+    int can_push;
+    unsigned long long seed;
+    const unsigned short* mlp;   // bf16 parameter block (LLP_MLP_PARAMS), device
+    float dense_frac;            // HYBRID: dense when changed out-arcs exceed this fraction of m
+};
+
+int sched_params(const llp_opts& o, bool can_push, SchedParams* sp);
+const unsigned short* learned_weights_device();
+
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) {
+    return __uint_as_float(((unsigned)h) << 16);
+}
+// round to nearest even
+__device__ __forceinline__ unsigned short f32_to_bf16(float f) {
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);   // inf / nan
+    unsigned lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float round_bf16(float f) { return bf16_to_f32(f32_to_bf16(f)); }
+
+// The 12 round features (all lanes compute the same values).
+__device__ __forceinline__ void round_features(float f[12], int r, int cl_count, int cl_edges, int n, int m,
+                                               const SchedHist& h) {
+    const float ln = __log2f(1.0f + (float)n), lm = __log2f(1.0f + (float)m);
+    const float davg = (float)m / (float)(n > 0 ? n : 1);
+    f[0] = __log2f(1.0f + (float)cl_count) / ln;
+    f[1] = __log2f(1.0f + (float)cl_edges) / (lm > 0.f ? lm : 1.f);
+    f[2] = (float)cl_count / (float)n;
+    f[3] = m > 0 ? (float)cl_edges / (float)m : 0.f;
+    f[4] = (cl_count > 0 ? (float)cl_edges / (float)cl_count : 0.f) / (davg > 0.f ? davg : 1.f);
+    f[5] = __log2f(1.0f + (float)h.wl_count) / ln;
+    f[6] = m > 0 ? (float)h.wl_edges / (float)m : 0.f;
+    f[7] = __log2f(1.0f + (float)cl_count) - __log2f(1.0f + (float)h.cl_count);
+    f[8] = h.mode == 2 ? 1.f : 0.f;
+    f[9] = h.mode == 1 ? 1.f : 0.f;
+    f[10] = (float)r / (float)(r + 16);
+    f[11] = (float)h.adv_total / (float)n;
+    for (int i = 0; i < 12; ++i) f[i] = round_bf16(f[i]);
+}
+
+// Wave-level MLP forward: out[5] logits in every lane.
+__device__ inline void mlp_forward_wave(const unsigned short* P, const float f[12], float out[5]) {
+    const int j = lane();
+    const unsigned short* W1 = P;
+    const unsigned short* b1 = W1 + 64 * 12;
+    const unsigned short* W2 = b1 + 64;
+    const unsigned short* b2 = W2 + 64 * 64;
+    const unsigned short* W3 = b2 + 64;
+    const unsigned short* b3 = W3 + 5 * 64;
+    float a = bf16_to_f32(b1[j]);
+    for (int k = 0; k < 12; ++k) a += bf16_to_f32(W1[j * 12 + k]) * f[k];
+    float h1 = round_bf16(fmaxf(a, 0.f));
+    float a2 = bf16_to_f32(b2[j]);
+    for (int k = 0; k < 64; ++k) a2 += bf16_to_f32(W2[j * 64 + k]) * __shfl(h1, k, 64);
+    float h2 = round_bf16(fmaxf(a2, 0.f));
+    for (int o = 0; o < 5; ++o) {
+        float t = bf16_to_f32(W3[o * 64 + j]) * h2;
+        for (int d = 32; d >= 1; d >>= 1) t += __shfl_xor(t, d, 64);
+        out[o] = t + bf16_to_f32(b3[o]);
+    }
+}
+
+__device__ __forceinline__ unsigned long long mix64d(unsigned long long z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Mode of round r: 0 pull (worklist), 1 dense pull, 2 push.  Call from a
+// whole wave; the result is wave-uniform.
+__device__ inline int decide_mode(const SchedParams& sp, const SchedHist& h, int r, int cl_count, int cl_edges,
+                                  int n, int m, int force_dense) {
+    if (force_dense) return 1;
+    switch (sp.sched) {
+        case LLP_SCHED_FIXED:
+            if (sp.flags & LLP_DENSE) return 1;
+            if ((sp.flags & LLP_PUSH) && sp.can_push) return 2;
+            return 0;
+        case LLP_SCHED_HYBRID:
+            return (float)cl_edges > sp.dense_frac * (float)m ? 1 : 0;
+        case LLP_SCHED_RANDOM: {
+            unsigned long long z = mix64d(sp.seed * 0x9E3779B97F4A7C15ull + (unsigned long long)r);
+            int k = (int)(z % (unsigned long long)(sp.can_push ? 3 : 2));
+            return k;
+        }
+        case LLP_SCHED_LEARNED: {
+            if (!sp.mlp) return 0;
+            float f[12], o[5];
+            round_features(f, r, cl_count, cl_edges, n, m, h);
+            mlp_forward_wave(sp.mlp, f, o);
+            if (o[0] > 0.f && sp.can_push) return 2;
+            if (o[1] > 0.f) return 1;
+            return 0;
+        }
+        default:
+            return 0;
+    }
+}
+
+// Record round r's input list in the history slot for the next decision.
+__device__ __forceinline__ void hist_push(SchedHist& dst, const SchedHist& prev, int r, int mode, int cl_count,
+                                          int cl_edges) {
+    dst.r = r;
+    dst.mode = mode;
+    dst.cl_count = cl_count;
+    dst.cl_edges = cl_edges;
+    dst.wl_count = 0;
+    dst.wl_edges = 0;
+    dst.adv_total = prev.adv_total + cl_count;
+}
+
+}  // namespace llp
