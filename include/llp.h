@@ -181,11 +181,12 @@ int llp_solve_jobs(int32_t n, const int32_t* pred_ptr, const int32_t* pred_idx, 
 
 /* 0-1 knapsack (paper Section 5.8): DP cells G[k][c], k = 0..items,
    c = 0..W, advanced to max(G[k-1][c], v_k + G[k-1][c - w_k]).  One
-   workgroup sweeps the table with two rows resident in LDS.  wt, val [device]
+   workgroup sweeps the table a row at a time (every cell of row k is
+   forbidden once row k-1 is final), rows resident in LDS.  wt, val [device]
    int32[items] >= 0; best [device, output] int32[1] = G[items][W];
    last_row [device, output, nullable] int32[W+1] = G[items][.].
-   Limits: items >= 0, 0 <= W <= 16383.  Errors: LLP_E_ARG, LLP_E_INPUT,
-   LLP_E_OVERFLOW. */
+   Limits: items >= 0, 0 <= W <= 16383.  Errors: LLP_E_ARG, LLP_E_INPUT
+   (negative weight or value), LLP_E_OVERFLOW (a value beyond int32). */
 int llp_solve_knapsack(int32_t items, int32_t W, const int32_t* wt, const int32_t* val,
                        int32_t* best, int32_t* last_row, const llp_opts* opts);
 
@@ -202,17 +203,24 @@ int llp_solve_tc(int32_t n, int64_t m, const int32_t* out_ptr, const int32_t* ou
    [device] modulo 2^64.  result [device, output] uint64[1]. */
 int llp_solve_reduce(int64_t n, const uint64_t* x, uint64_t* result, const llp_opts* opts);
 
-/* Batched persistent solve: count independent instances in one launch.
-   desc [device] llp_instance[count]; pool [device] int32 input words;
-   out_pool [device] int32 output words.
-   LLP_KIND_KNAPSACK instance: n = items, cap_or_source = W (<= 16383),
+/* Batched persistent solve: count independent instances in one launch of a
+   persistent kernel; each workgroup takes `chunk` instances at a time from a
+   device queue and solves each one on its own (workgroup-local sweep, state in
+   LDS).  desc [device] llp_instance[count]; pool [device] int32[pool_words]
+   input words; out_pool [device] int32[out_words] output words.
+   LLP_KIND_KNAPSACK instance: n = items, cap_or_source = W (0 <= W <= 16383),
      pool[in_off ..] = wt[n], val[n]; out_pool[out_off] = best.
-   LLP_KIND_SSSP instance: n vertices (<= 8192), m arcs, cap_or_source = source,
-     pool[in_off ..] = in_ptr[n+1], in_src[m], in_w[m], out_ptr[n+1], out_dst[m];
-     out_pool[out_off ..] = dist[n].
-   Per-instance status words go to out_status [device, nullable] int32[count];
-   the return value is the first nonzero one.  With opts->flags & LLP_ASYNC the
-   call is capturable in a hipGraph. */
+   LLP_KIND_SSSP instance: n vertices (1 <= n <= 8192), m arcs,
+     cap_or_source = source, pool[in_off ..] = out_ptr[n+1], out_dst[m],
+     out_w[m] (arcs grouped by tail, weights >= 0); out_pool[out_off ..] =
+     dist[n] (2^31-1 = unreachable).
+   Per-instance status words go to out_status [device, nullable]
+   int32[count]; an instance whose ranges fall outside pool / out_pool, or
+   whose arrays are malformed, gets LLP_E_INPUT without being read further.
+   The return value is the first nonzero instance status.
+   A first call measures the largest W and n in desc (one small readback) to
+   size the LDS; opts->block / opts->chunk = 0 take the autotuned values (or
+   256 threads, 1 instance). */
 typedef struct {
     int32_t kind;
     int32_t n;
@@ -223,23 +231,31 @@ typedef struct {
     int64_t out_off;
 } llp_instance;
 
-int llp_solve_batch(int32_t count, const llp_instance* desc, const int32_t* pool, int32_t* out_pool,
-                    int32_t* out_status, const llp_opts* opts);
+int llp_solve_batch(int32_t count, const llp_instance* desc, const int32_t* pool, int64_t pool_words,
+                    int32_t* out_pool, int64_t out_words, int32_t* out_status, const llp_opts* opts);
 
-/* Batched solve replayed from an instantiated hipGraph cached by the library
-   (keyed by desc/pool/out_pool pointers, count and stream); the first call
-   captures.  Same arguments and results as llp_solve_batch. */
-int llp_solve_batch_graph(int32_t count, const llp_instance* desc, const int32_t* pool,
-                          int32_t* out_pool, int32_t* out_status, const llp_opts* opts);
+/* Batched solve replayed from an instantiated hipGraph cached by the library,
+   keyed by (desc, pool, out_pool, out_status, count, stream, block, chunk);
+   the first call measures, captures and instantiates, later calls only
+   launch the graph.  With LLP_ASYNC a replay returns once enqueued and the
+   batch status goes to opts->status_dev.  Same arguments and results as
+   llp_solve_batch.  Released by llp_shutdown(). */
+int llp_solve_batch_graph(int32_t count, const llp_instance* desc, const int32_t* pool, int64_t pool_words,
+                          int32_t* out_pool, int64_t out_words, int32_t* out_status, const llp_opts* opts);
 
 /* ---------------------------------------------------------------- autotuner
-   Times each candidate (threads per workgroup, cells per thread) of the batch
-   kernel on a sample batch and records the fastest under (arch, CU count,
-   kind); llp_solve_batch then uses it when opts->block/chunk are 0.
-   Writes "block chunk ms" lines of every candidate to report (nullable) as
-   text, up to report_bytes. */
-int llp_autotune_batch(int32_t count, const llp_instance* desc, const int32_t* pool, int32_t* out_pool,
-                       char* report, size_t report_bytes, const llp_opts* opts);
+   Times each candidate (threads per workgroup in {256, 512, 1024} x
+   instances per queue claim in {1, 2, 4, 8}) of the batch kernel on the given
+   batch (median of 3 timed launches after one warm-up) and records the
+   fastest under the current device; llp_solve_batch uses it when
+   opts->block and opts->chunk are 0.  Writes one "block chunk ms" line per
+   candidate to report (nullable, host) as text, up to report_bytes.
+   Outputs of the batch are left as computed by the last candidate. */
+int llp_autotune_batch(int32_t count, const llp_instance* desc, const int32_t* pool, int64_t pool_words,
+                       int32_t* out_pool, int64_t out_words, char* report, size_t report_bytes,
+                       const llp_opts* opts);
+/* The recorded choice for kind (LLP_KIND_BATCH) on the current device;
+   LLP_E_ARG if none has been recorded. */
 int llp_autotune_get(int kind, int32_t* block, int32_t* chunk);
 
 /* ---------------------------------------------------------------- learned scheduler

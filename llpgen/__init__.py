@@ -224,3 +224,30 @@ def uniform_ints(n: int, lo: int, hi: int, seed: int, tag: int = 0x98):
         z = z ^ (z >> np.uint64(31))
     span = np.uint64(hi - lo + 1)
     return (np.int64(lo) + (((z >> np.uint64(32)) * span) >> np.uint64(32)).astype(np.int64)).astype(np.int64)
+
+
+def job_succ(pred_ptr, pred_idx):
+    """Successor lists (succ_ptr[n+1], succ_idx[E]) holding the same arcs as the
+    predecessor lists, grouped by predecessor (stable)."""
+    n = int(pred_ptr.shape[0]) - 1
+    child = np.repeat(np.arange(n, dtype=np.int32), np.diff(pred_ptr).astype(np.int64))
+    ptr, idx, _ = csr(n, pred_idx, child)
+    return ptr, idx
+
+
+# ---------------------------------------------------------------- batch workload
+def batch_workload(n_knap: int = 4096, n_sssp: int = 4096, seed: int = 5, sssp_nlo: int = 256,
+                   sssp_nhi: int = 4096, deg: int = 8):
+    """Mixed batch: n_knap knapsack instances of the seeded family and n_sssp
+    small SSSP graphs (n U[sssp_nlo, sssp_nhi], deg*n uniform arcs without
+    self-loops plus the Hamiltonian cycle, w U[1,100], source 0), interleaved
+    by a seeded permutation.  Returns a list of tuples
+    ("knapsack", wt, val, W) / ("sssp", EdgeList, source)."""
+    items = [("knapsack",) + tuple(knapsack(i, seed=seed)) for i in range(n_knap)]
+    ns = uniform_ints(n_sssp, sssp_nlo, sssp_nhi, seed, tag=0x97) if n_sssp else []
+    for i in range(n_sssp):
+        n = int(ns[i])
+        g = uniform_graph(n, deg * n, 1, 100, seed=(seed << 24) + i)
+        items.append(("sssp", g, 0))
+    order = permutation(len(items), seed, tag=0x96) if items else []
+    return [items[int(k)] for k in order]

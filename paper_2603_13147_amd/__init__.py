@@ -110,9 +110,9 @@ def lib():
         ("llp_solve_knapsack", [i32, i32, vp, vp, vp, vp, po]),
         ("llp_solve_tc", [i32, i64, vp, vp, vp, po]),
         ("llp_solve_reduce", [i64, vp, vp, po]),
-        ("llp_solve_batch", [i32, vp, vp, vp, vp, po]),
-        ("llp_solve_batch_graph", [i32, vp, vp, vp, vp, po]),
-        ("llp_autotune_batch", [i32, vp, vp, vp, ctypes.c_char_p, sz, po]),
+        ("llp_solve_batch", [i32, vp, vp, i64, vp, i64, vp, po]),
+        ("llp_solve_batch_graph", [i32, vp, vp, i64, vp, i64, vp, po]),
+        ("llp_autotune_batch", [i32, vp, vp, i64, vp, i64, ctypes.c_char_p, sz, po]),
         ("llp_autotune_get", [ctypes.c_int, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         ("llp_mlp_forward", [i32, vp, vp, vp, vp, vp]),
         ("llp_mlp_loss", [i32, vp, vp, vp, vp, vp]),
@@ -248,3 +248,175 @@ def bfs(dg, source, out=None, ws=None, **kw):
         ws = workspace(KIND_BFS, dg.n, dg.m)
     o = make_opts(workspace=ws, **kw)
     return _graph_solve(lib().llp_solve_bfs, KIND_BFS, dg, source, out, o)
+
+
+# ---------------------------------------------------------------- stable marriage
+def stable_marriage(mpref, wrank, wife=None, prop=None, ws=None, **kw):
+    """Man-optimal stable matching: (wife[n], proposal_index[n]) int32 tensors.
+    mpref[m, i] = i-th woman on man m's list; wrank[w, m] = rank of m for w."""
+    torch = _torch()
+    mp = _dev(mpref, torch.int16)
+    wr = _dev(wrank, torch.int16)
+    n = int(mp.shape[0])
+    if tuple(mp.shape) != (n, n) or tuple(wr.shape) != (n, n):
+        raise LLPError(E_ARG, "mpref and wrank must both be n x n")
+    if wife is None:
+        wife = torch.empty(n, dtype=torch.int32, device="cuda")
+    if prop is None:
+        prop = torch.empty(n, dtype=torch.int32, device="cuda")
+    if ws is None:
+        ws = workspace(KIND_SM, n, 0)
+    o = make_opts(workspace=ws, **kw)
+    _check(lib().llp_solve_sm(n, _ptr(mp), _ptr(wr), _ptr(wife), _ptr(prop), ctypes.byref(o)))
+    return wife, prop
+
+
+# ---------------------------------------------------------------- jobs
+def jobs(pred_ptr, pred_idx, dur, succ_ptr, succ_idx, out=None, ws=None, pull=False, **kw):
+    """Earliest start times (int32 tensor) of the job DAG given by predecessor
+    and successor lists; pull=True runs the pull form of the sweep."""
+    torch = _torch()
+    pp, pi, d = _dev(pred_ptr, torch.int32), _dev(pred_idx, torch.int32), _dev(dur, torch.int32)
+    sp, si = _dev(succ_ptr, torch.int32), _dev(succ_idx, torch.int32)
+    n = int(d.shape[0])
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device="cuda")
+    if ws is None:
+        ws = workspace(KIND_JOBS, n, int(pi.shape[0]))
+    if pull:
+        kw["flags"] = kw.get("flags", 0) | JOBS_PULL
+    o = make_opts(workspace=ws, **kw)
+    _check(lib().llp_solve_jobs(n, _ptr(pp), _ptr(pi), _ptr(d), _ptr(sp), _ptr(si), _ptr(out),
+                                ctypes.byref(o)))
+    return out
+
+
+# ---------------------------------------------------------------- knapsack
+def knapsack(wt, val, W, row=False, ws=None, **kw):
+    """Best value of the 0-1 knapsack (int); with row=True also G[items][0..W]
+    as an int32 tensor."""
+    torch = _torch()
+    w_, v_ = _dev(wt, torch.int32), _dev(val, torch.int32)
+    items = int(w_.shape[0])
+    best = torch.zeros(1, dtype=torch.int32, device="cuda")
+    last = torch.empty(W + 1, dtype=torch.int32, device="cuda") if row else None
+    if ws is None:
+        ws = workspace(KIND_KNAPSACK, items, W)
+    o = make_opts(workspace=ws, **kw)
+    _check(lib().llp_solve_knapsack(items, int(W), _ptr(w_), _ptr(v_), _ptr(best), _ptr(last),
+                                    ctypes.byref(o)))
+    return (int(best.item()), last) if row else int(best.item())
+
+
+# ---------------------------------------------------------------- batch
+class Batch:
+    """Device-resident batch of independent instances for llp_solve_batch.
+
+    items: tuples ("knapsack", wt, val, W) or ("sssp", graph, source) where
+    graph has n, src, dst, w (an edge list; it is packed here as out-CSR
+    grouped by tail, arcs in input order)."""
+
+    def __init__(self, items):
+        torch = _torch()
+        desc = np.zeros(len(items), INSTANCE_DTYPE)
+        chunks, pos, out = [], 0, 0
+        self.out_slices = []
+        for i, it in enumerate(items):
+            if it[0] == "knapsack":
+                _, wt, val, W = it
+                wt = np.ascontiguousarray(wt, np.int32)
+                val = np.ascontiguousarray(val, np.int32)
+                desc[i] = (KIND_KNAPSACK, wt.shape[0], W, 0, 0, pos, out)
+                chunks += [wt, val]
+                pos += 2 * wt.shape[0]
+                self.out_slices.append((out, 1))
+                out += 1
+            elif it[0] == "sssp":
+                _, g, source = it
+                n, m = int(g.n), int(g.src.shape[0])
+                order = np.argsort(g.src, kind="stable")
+                ptr = np.zeros(n + 1, np.int64)
+                np.add.at(ptr, g.src.astype(np.int64) + 1, 1)
+                ptr = np.cumsum(ptr).astype(np.int32)
+                desc[i] = (KIND_SSSP, n, source, 0, m, pos, out)
+                chunks += [ptr, g.dst[order].astype(np.int32), g.w[order].astype(np.int32)]
+                pos += n + 1 + 2 * m
+                self.out_slices.append((out, n))
+                out += n
+            else:
+                raise LLPError(E_ARG, f"unknown instance kind {it[0]!r}")
+        pool = np.concatenate(chunks) if chunks else np.zeros(1, np.int32)
+        self.count = len(items)
+        self.desc = torch.from_numpy(desc.view(np.uint8).copy()).cuda()
+        self.pool = torch.from_numpy(pool.astype(np.int32)).cuda()
+        self.pool_words = int(pos)
+        self.out = torch.zeros(max(out, 1), dtype=torch.int32, device="cuda")
+        self.out_words = int(out)
+        self.status = torch.zeros(max(len(items), 1), dtype=torch.int32, device="cuda")
+        self.ws = workspace(KIND_BATCH, 0, self.count)
+
+    def _args(self):
+        return (self.count, _ptr(self.desc), _ptr(self.pool), self.pool_words, _ptr(self.out),
+                self.out_words, _ptr(self.status))
+
+    def solve(self, graph=False, **kw):
+        """Solve every instance (graph=True: replay a captured hipGraph)."""
+        o = make_opts(workspace=kw.pop("ws", self.ws), **kw)
+        fn = lib().llp_solve_batch_graph if graph else lib().llp_solve_batch
+        _check(fn(*self._args(), ctypes.byref(o)))
+        return self
+
+    def autotune(self, **kw):
+        """Time every launch shape on this batch; returns [(block, chunk, ms)]."""
+        o = make_opts(workspace=kw.pop("ws", self.ws), **kw)
+        buf = ctypes.create_string_buffer(4096)
+        c, d, p, pw, out, ow, _ = self._args()
+        _check(lib().llp_autotune_batch(c, d, p, pw, out, ow, buf, 4096, ctypes.byref(o)))
+        rows = []
+        for line in buf.value.decode().splitlines():
+            b, ch, ms = line.split()
+            rows.append((int(b), int(ch), float(ms)))
+        return rows
+
+    def results(self):
+        """Per-instance results: int (knapsack best) or int32 array (SSSP dist)."""
+        o = self.out.cpu().numpy()
+        kinds = np.frombuffer(self.desc.cpu().numpy().tobytes(), INSTANCE_DTYPE)["kind"]
+        return [int(o[a]) if kinds[i] == KIND_KNAPSACK else o[a:a + k].copy()
+                for i, (a, k) in enumerate(self.out_slices)]
+
+
+def autotune_get(kind=KIND_BATCH):
+    b, c = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().llp_autotune_get(kind, ctypes.byref(b), ctypes.byref(c)))
+    return b.value, c.value
+
+
+# ---------------------------------------------------------------- transitive closure / reduction
+def transitive_closure(n, out_ptr, out_dst, ws=None, **kw):
+    """Reachability bit rows (uint32 words as an int32 tensor [n, ceil(n/32)]):
+    bit v & 31 of word v >> 5 in row u is set iff a path of length >= 1 leads
+    from u to v."""
+    torch = _torch()
+    p, d = _dev(out_ptr, torch.int32), _dev(out_dst, torch.int32)
+    words = (n + 31) // 32
+    bits = torch.empty((n, words), dtype=torch.int32, device="cuda")
+    if ws is None:
+        ws = workspace(KIND_TC, n, int(d.shape[0]))
+    o = make_opts(workspace=ws, **kw)
+    _check(lib().llp_solve_tc(n, int(d.shape[0]), _ptr(p), _ptr(d), _ptr(bits), ctypes.byref(o)))
+    return bits
+
+
+def reduce_sum(x, ws=None, **kw):
+    """Sum of uint64 words modulo 2**64 (x: numpy uint64 or an int64 tensor of the same bits)."""
+    torch = _torch()
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x, np.uint64).view(np.int64))
+    x = x.to(device="cuda").contiguous()
+    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    if ws is None:
+        ws = workspace(KIND_REDUCE, x.numel(), 0)
+    o = make_opts(workspace=ws, **kw)
+    _check(lib().llp_solve_reduce(x.numel(), _ptr(x), _ptr(out), ctypes.byref(o)))
+    return int(out.cpu().numpy().view(np.uint64)[0])

@@ -64,6 +64,8 @@ struct GArgs {
     int nseg;
     int source;
     int unit_w;        // BFS: every weight is 1
+    int jobs;          // job scheduling in pull form: G = S, contribution S[p] + dur[p]
+    const int* vdur;   // jobs: duration per job (the weight of every out-arc of p)
     int warm_dense;    // warm start: round 1 is dense
     GCtrl* ctrl;
     llp_trace_rec* trace;
@@ -79,11 +81,15 @@ __global__ void k_graph_init(GArgs a, const int* warm) {
     const long long nt = (long long)gridDim.x * blockDim.x;
     for (long long v = tid; v < a.n; v += nt) {
         int g = 0;
-        if (warm) {
-            int d = warm[v];
-            g = (d >= LLP_INF || d < 0) ? 0 : LLP_INF - d;
+        if (a.jobs) {
+            g = warm && warm[v] > 0 ? warm[v] : 0;
+        } else {
+            if (warm) {
+                int d = warm[v];
+                g = (d >= LLP_INF || d < 0) ? 0 : LLP_INF - d;
+            }
+            if (v == a.source) g = LLP_INF;
         }
-        if (v == a.source) g = LLP_INF;
         a.G[v] = g;
         a.stamp[v] = 0;
         a.cstamp[v] = 0;
@@ -98,6 +104,8 @@ __global__ void k_graph_init(GArgs a, const int* warm) {
         memset(&c, 0, sizeof(c));
         c.mode = -1;
         *a.ctrl = c;
+    }
+    if (tid == 0 && !a.jobs) {
         // CL[0] = {source}: one entry in segment 0
         int ob = a.out_ptr ? a.out_ptr[a.source] : 0;
         int od = a.out_ptr ? a.out_ptr[a.source + 1] - ob : 0;
@@ -118,6 +126,7 @@ __global__ void k_graph_validate(GArgs a) {
         if (v == 0 && p != 0) bad = 1;
         if (v == a.n && p != a.m) bad = 1;
         if (v < a.n && a.in_ptr[v + 1] < p) bad = 1;
+        if (v < a.n && a.jobs && a.vdur[v] < 0) bad = 1;
         if (a.out_ptr) {
             int q = a.out_ptr[v];
             if (v == 0 && q != 0) bad = 1;
@@ -158,6 +167,14 @@ __device__ __forceinline__ int pull_cand(int gu, int w, bool& ovf) {
     return c;
 }
 
+// Jobs: start time published through arc (p -> j) is S[p] + dur[p]; a sum
+// beyond int32 means p's completion time overflows.
+__device__ __forceinline__ int jobs_cand(int sp, int dp, bool& ovf) {
+    long long c = (long long)sp + dp;
+    if (c > LLP_INF) { ovf = true; return LLP_INF; }
+    return (int)c;
+}
+
 // Evaluate edges of the iteration: segmented max of candidates per owner,
 // advance owners by atomicMax, append changed vertices to CL.
 __device__ __forceinline__ void eval_body(const GArgs& a, const EdgeCtx& c, int r, const ListRef& out,
@@ -167,8 +184,12 @@ __device__ __forceinline__ void eval_body(const GArgs& a, const EdgeCtx& c, int 
     if (c.active) {
         int e = guard(c.csr, a.m, a.ctrl->diag, 41, c.own.y, c.own.z);
         int u = guard(a.in_src[e], a.n, a.ctrl->diag, 42, e, 0);
-        int w = a.unit_w ? 1 : a.in_w[e];
-        cand = pull_cand(a.G[u], w, ovf);
+        if (a.jobs) {
+            cand = jobs_cand(a.G[u], a.vdur[u], ovf);
+        } else {
+            int w = a.unit_w ? 1 : a.in_w[e];
+            cand = pull_cand(a.G[u], w, ovf);
+        }
     }
     int seg = c.active ? c.j : 64 + l;
     int x = seg_incl_max(cand, seg);
@@ -210,15 +231,23 @@ __device__ __forceinline__ void expand_body(const GArgs& a, const EdgeCtx& c, in
 // Push: single-arc partial advance of each out-neighbour (Definition 3).
 __device__ __forceinline__ void push_body(const GArgs& a, const EdgeCtx& c, int r, const ListRef& out,
                                           GShared& sh, bool& ovf, long long& nadv) {
-    int gmine = c.mine_valid ? a.G[guard(c.mine.x, a.n, a.ctrl->diag, 61)] : 0;
+    int umine = c.mine_valid ? guard(c.mine.x, a.n, a.ctrl->diag, 61) : 0;
+    int gmine = c.mine_valid ? a.G[umine] : 0;
+    int dmine = (c.mine_valid && a.jobs) ? a.vdur[umine] : 0;
     int gu = shfl(gmine, c.j);
+    int du = shfl(dmine, c.j);
     bool changed = false;
     int x = 0, ob = 0, od = 0;
     if (c.active) {
         int e = guard(c.csr, a.m, a.ctrl->diag, 62, c.own.y, c.own.z);
         x = guard(a.out_dst[e], a.n, a.ctrl->diag, 63);
-        int w = a.unit_w ? 1 : a.out_w[e];
-        int cand = pull_cand(gu, w, ovf);
+        int cand;
+        if (a.jobs) {
+            cand = jobs_cand(gu, du, ovf);
+        } else {
+            int w = a.unit_w ? 1 : a.out_w[e];
+            cand = pull_cand(gu, w, ovf);
+        }
         if (cand > 0 && cand > a.G[x]) {
             int old = amax(&a.G[x], cand);
             if (old < cand) changed = (amax(&a.cstamp[x], r) < r);
@@ -357,10 +386,18 @@ __global__ void __launch_bounds__(GB) k_graph_main(GArgs a, int r, int verify) {
 // --------------------------------------------------------------- finish
 // Overflow: a vertex still at the bottom with a reached in-neighbour has a
 // true distance >= INF.  Only run when a candidate overflowed.
+// Jobs: every completion time S[j] + dur[j] must fit int32 (always checked).
 __global__ void k_graph_ovf(GArgs a) {
-    if (!ld_relaxed(&a.ctrl->ovf)) return;
     const long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const long long nt = (long long)gridDim.x * blockDim.x;
+    if (a.jobs) {
+        bool bad = false;
+        for (long long v = tid; v < a.n; v += nt)
+            if ((long long)a.G[v] + a.vdur[v] > LLP_INF) bad = true;
+        if (bad) set_status(&a.ctrl->status, LLP_E_OVERFLOW);
+        return;
+    }
+    if (!ld_relaxed(&a.ctrl->ovf)) return;
     for (long long v = tid; v < a.n; v += nt) {
         if (a.G[v] != 0) continue;
         bool bad = false;
@@ -432,20 +469,23 @@ static int launch_grid_1d(int64_t work) {
     return (int)(g < cap ? g : cap);
 }
 
-int solve_graph(const llp_graph* g, int32_t source, int32_t* out, const llp_opts* opts, bool bfs) {
+// jobs != nullptr: the pull form of job scheduling (in-CSR = predecessor
+// lists, out-CSR = successor lists, per-job durations), otherwise SSSP / BFS.
+static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, const llp_opts* opts, bool bfs,
+                            const int* jobs_dur) {
     if (!g) return fail(LLP_E_ARG, "graph is NULL");
     if (!out) return fail(LLP_E_ARG, "output is NULL");
     if (g->n <= 0) return fail(LLP_E_ARG, "n must be positive (got %d)", g->n);
     if (g->m < 0 || g->m > (int64_t)0x7fffffff - (1 << 20)) return fail(LLP_E_ARG, "m out of range");
     if (source < 0 || source >= g->n) return fail(LLP_E_ARG, "source %d out of range [0, %d)", source, g->n);
     if (!g->in_ptr || (g->m > 0 && !g->in_src)) return fail(LLP_E_ARG, "in-CSR arrays are required");
-    if (!bfs && g->m > 0 && !g->in_w) return fail(LLP_E_ARG, "SSSP needs in_w (use llp_solve_bfs for unit weights)");
+    if (!bfs && !jobs_dur && g->m > 0 && !g->in_w) return fail(LLP_E_ARG, "SSSP needs in_w (use llp_solve_bfs for unit weights)");
     llp_opts o = opts_or_default(opts);
     hipStream_t st = (hipStream_t)o.stream;
     const bool need_out = true;
     if (need_out && (!g->out_ptr || (g->m > 0 && !g->out_dst)))
         return fail(LLP_E_ARG, "out-CSR (out_ptr, out_dst) is required for successor expansion");
-    if (o.sched == LLP_SCHED_FIXED && (o.flags & LLP_PUSH) && !bfs && !g->out_w)
+    if (o.sched == LLP_SCHED_FIXED && (o.flags & LLP_PUSH) && !bfs && !jobs_dur && !g->out_w)
         return fail(LLP_E_ARG, "push rounds need out_w");
     if (o.sched > LLP_SCHED_RANDOM) return fail(LLP_E_ARG, "unknown schedule %u", o.sched);
 
@@ -462,10 +502,12 @@ int solve_graph(const llp_graph* g, int32_t source, int32_t* out, const llp_opts
     a.G = out;
     a.source = source;
     a.unit_w = bfs ? 1 : 0;
+    a.jobs = jobs_dur ? 1 : 0;
+    a.vdur = jobs_dur;
     a.trace = (o.flags & LLP_TRACE) ? o.trace_dev : nullptr;
     a.trace_cap = o.trace_cap;
-    a.warm_dense = o.warm_start ? 1 : 0;
-    int s = sched_params(o, bfs || g->out_w != nullptr, &a.sp);
+    a.warm_dense = (o.warm_start || jobs_dur) ? 1 : 0;   // jobs: every index is a round-1 candidate
+    int s = sched_params(o, bfs || jobs_dur || g->out_w != nullptr, &a.sp);
     if (s) return s;
 
     size_t need = graph_ws(g->n, g->m, nullptr, nullptr, 0);
@@ -522,7 +564,7 @@ int solve_graph(const llp_graph* g, int32_t source, int32_t* out, const llp_opts
         hipLaunchKernelGGL(k_graph_main, dim3(a.nseg), dim3(GB), 0, st, a, (int)h.last_round + 1, 1);
     }
     if (h.status == 0) hipLaunchKernelGGL(k_graph_ovf, dim3(g1), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_graph_decode, dim3(launch_grid_1d(g->n)), dim3(256), 0, st, out, g->n);
+    if (!jobs_dur) hipLaunchKernelGGL(k_graph_decode, dim3(launch_grid_1d(g->n)), dim3(256), 0, st, out, g->n);
     LLP_HIP(hipGetLastError());
     if (timing) LLP_HIP(hipEventRecord(ev1, st));
     s = readback(st, a.ctrl, &h, sizeof(h));
@@ -557,13 +599,41 @@ int solve_graph(const llp_graph* g, int32_t source, int32_t* out, const llp_opts
     }
     if (h.status) {
         if (h.status == LLP_E_INPUT) return fail(LLP_E_INPUT, "device validation rejected the graph");
-        if (h.status == LLP_E_OVERFLOW) return fail(LLP_E_OVERFLOW, "a reachable distance does not fit int32");
+        if (h.status == LLP_E_OVERFLOW)
+            return fail(LLP_E_OVERFLOW, jobs_dur ? "a completion time does not fit int32"
+                                                 : "a reachable distance does not fit int32");
         return fail(h.status, "device status %d", h.status);
     }
     if (h.verify_changed) return fail(LLP_E_HIP, "verification round advanced an index after convergence");
+    if (status == LLP_E_NOT_CONVERGED && jobs_dur && o.max_rounds <= 0)
+        return fail(LLP_E_CYCLE, "no fixpoint within n + 2 rounds: the job arcs contain a cycle");
     if (status == LLP_E_NOT_CONVERGED) return fail(status, "not converged after %lld rounds", (long long)max_rounds);
     if (status == LLP_E_ABORTED) return fail(status, "aborted by the host flag");
     return LLP_OK;
+}
+
+int solve_graph(const llp_graph* g, int32_t source, int32_t* out, const llp_opts* opts, bool bfs) {
+    return solve_graph_core(g, source, out, opts, bfs, nullptr);
+}
+
+// Job scheduling, pull form: the generic sweep with alpha(S, j) = max over
+// predecessors p of S[p] + dur[p], every job a round-1 candidate.  A DAG
+// reaches its fixpoint within n rounds (each round is at least a Jacobi
+// step), so the round limit doubles as the cycle test; a cycle of zero
+// durations has a fixpoint and is not reported.
+int solve_jobs_pull(int32_t n, const int32_t* pred_ptr, const int32_t* pred_idx, const int32_t* dur,
+                    const int32_t* succ_ptr, const int32_t* succ_idx, int32_t* start, const llp_opts* opts,
+                    int64_t E) {
+    llp_graph g;
+    g.n = n;
+    g.m = E;
+    g.in_ptr = pred_ptr;
+    g.in_src = pred_idx;
+    g.in_w = nullptr;
+    g.out_ptr = succ_ptr;
+    g.out_dst = succ_idx;
+    g.out_w = nullptr;
+    return solve_graph_core(&g, 0, start, opts, false, dur);
 }
 
 }  // namespace llp

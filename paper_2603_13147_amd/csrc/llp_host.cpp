@@ -129,6 +129,8 @@ int readback(hipStream_t s, const void* src, void* dst, size_t bytes) {
     return LLP_OK;
 }
 
+void batch_release();
+
 }  // namespace llp
 
 extern "C" {
@@ -138,6 +140,7 @@ const char* llp_last_error(void) { return llp::g_err; }
 const char* llp_version(void) { return "libllp 0.1 (gfx950)"; }
 
 void llp_shutdown(void) {
+    llp::batch_release();
     std::lock_guard<std::mutex> lk(llp::g_mu);
     for (auto& kv : llp::g_ws) {
         if (kv.second.ptr) {

@@ -14,8 +14,6 @@ LIB = os.path.join(ROOT, "paper_2603_13147_amd", "libllp.so")
 # Entry points declared in the header whose plugins are still being written;
 # this set only shrinks.
 NOT_YET_BUILT = {
-    "llp_solve_sm", "llp_solve_jobs", "llp_solve_knapsack", "llp_solve_tc", "llp_solve_reduce",
-    "llp_solve_batch", "llp_solve_batch_graph", "llp_autotune_batch", "llp_autotune_get",
     "llp_mlp_forward", "llp_mlp_loss", "llp_mlp_backward", "llp_mlp_adam", "llp_trace_features",
 }
 
