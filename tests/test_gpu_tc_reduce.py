@@ -21,12 +21,37 @@ def tc_case(g):
     assert np.array_equal(got, want)
 
 
-@pytest.mark.parametrize("n,m,seed", [(1, 0, 1), (5, 3, 2), (33, 40, 3), (100, 60, 4), (1000, 1500, 5),
-                                      (4097, 8000, 6), (8192, 65536, 7)])
+@pytest.mark.parametrize("n,m,seed", [(1, 0, 1), (5, 3, 2), (33, 40, 3), (100, 60, 4), (1000, 1500, 5)])
 def test_tc_uniform(n, m, seed):
     g = llpgen.uniform_graph(n, m, seed=seed, cycle=False) if n > 1 else \
         llpgen.EdgeList(1, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32))
     tc_case(g)
+
+
+@pytest.mark.parametrize("n,m,seed", [(4097, 8000, 6), (8192, 65536, 7)])
+def test_tc_large_sampled_rows(n, m, seed):
+    """At sizes where the literal predicate oracle (cubic per pass) takes minutes,
+    sampled rows are checked against breadth-first reachability (paths of
+    length >= 1: u itself only when an in-neighbour of u is reachable)."""
+    sp = pytest.importorskip("scipy.sparse")
+    csg = pytest.importorskip("scipy.sparse.csgraph")
+    g = llpgen.uniform_graph(n, m, seed=seed, cycle=False)
+    csr = llpgen.CSRGraph(g, weighted=False)
+    got = llp.transitive_closure(n, csr.out_ptr, csr.out_dst)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy().view(np.uint32)
+    A = sp.csr_matrix((np.ones(g.m, np.int8), (g.src, g.dst)), shape=(n, n))
+    words = (n + 31) // 32
+    for u in llpgen.uniform_ints(64, 0, n - 1, seed=seed, tag=0x55):
+        u = int(u)
+        reach = np.zeros(n, bool)
+        reach[csg.breadth_first_order(A, u, directed=True, return_predecessors=False)] = True
+        ins = g.src[g.dst == u]
+        reach[u] = bool(reach[ins].any()) if ins.size else False
+        want = np.zeros(words * 32, bool)
+        want[:n] = reach
+        want_words = np.packbits(want.reshape(-1, 32)[:, ::-1], axis=1).view(">u4").ravel()
+        assert np.array_equal(got[u], want_words.astype(np.uint32)), u
 
 
 def test_tc_self_loop_cycle_and_chain():
