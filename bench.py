@@ -38,6 +38,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--scale", type=int, default=22)
     p.add_argument("--sched", default="plain", choices=["plain", "hybrid", "dense", "push", "learned"])
+    p.add_argument("--delta", type=int, default=0,
+                   help="delta-bucket width for the fixed schedules (plain becomes fixed pull)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--profile-steps", type=int, default=0,
                    help="run only this many steps, no baseline (for rocprofv3 runs)")
@@ -70,6 +72,10 @@ def main():
              "dense": dict(sched=llp.SCHED_FIXED, flags=llp.DENSE),
              "push": dict(sched=llp.SCHED_FIXED, flags=llp.PUSH),
              "learned": dict(sched=llp.SCHED_LEARNED)}[a.sched]
+    if a.delta > 0:
+        if sched["sched"] == llp.SCHED_PLAIN:
+            sched = dict(sched=llp.SCHED_FIXED)
+        sched["delta"] = a.delta
     if a.sched == "learned":
         wpath = os.path.join(ROOT, "paper_2603_13147_amd", "sched_weights.npy")
         llp.set_sched_weights(np.load(wpath))
@@ -128,7 +134,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"rmat-scale{a.scale} sssp+bfs (a,b,c,d)=(.57,.19,.19,.05), relabelled, "
                                f"+hamiltonian cycle, w U[1,255] / unit, source max-outdeg",
-                   "n": n, "m": m, "schedule": a.sched},
+                   "n": n, "m": m, "schedule": a.sched + (f"+delta{a.delta}" if a.delta else "")},
         "sssp": {"gteps": round(m / (sssp_ms * 1e-3) / 1e9, 4), "ms": round(float(sssp_ms), 3),
                  "rounds": s1.rounds, "edges_inspected": s1.edges_inspected,
                  "expand_edges": s1.expand_edges, "candidates": s1.candidates},

@@ -56,7 +56,20 @@ typedef enum {
 #define LLP_SCHED_FIXED   1u  /* the mode given by flags (LLP_PUSH / LLP_DENSE) and delta, every round */
 #define LLP_SCHED_LEARNED 2u  /* per round, the loaded MLP picks push/pull, dense/worklist and delta */
 #define LLP_SCHED_HYBRID  3u  /* per round, a frontier-width threshold picks dense vs worklist */
-#define LLP_SCHED_RANDOM  4u  /* per round, a seeded random mode (schedule-independence tests) */
+#define LLP_SCHED_RANDOM  4u  /* per round, a seeded random mode and delta class (schedule-independence tests) */
+#define LLP_SCHED_SCRIPT  5u  /* per round, the code opts->plan[r-1] (plain after the plan ends); used to
+                                 measure what a decision at a given round costs when training the scheduler */
+
+/* Round codes (llp_trace_rec.mode, opts->plan): bits 0-1 the mode (0 pull over
+   the candidate worklist, 1 dense pull, 2 push), bits 8-9 the delta class:
+   0 = the base width (2^floor(log2 of the mean arc weight), estimated from a
+   sample of the arcs; 1 for BFS), 1 = 8 x the base width, 2 = no buckets,
+   3 = opts->delta.  With a delta width D, a round only expands (or pushes
+   from) the changed vertices whose distance lies below floor(dmin / D) * D + D,
+   dmin the smallest distance among them; the others are carried to the next
+   round (delta-stepping buckets, paper Section 4.2).  Dense rounds ignore
+   the buckets. */
+#define LLP_ROUND_CODE(mode, dclass) ((int32_t)((mode) | ((dclass) << 8)))
 
 /* Flags. */
 #define LLP_PUSH      (1u << 0)  /* FIXED: push single-arc partial advances along out-arcs */
@@ -84,20 +97,20 @@ typedef struct {
 typedef struct {
     int32_t round;
     int32_t mode;             /* bit 0 push, bit 1 dense, bits 8.. delta class */
-    int32_t in_count;         /* indices in the round's input list */
-    int32_t out_count;        /* indices in the round's output list (changed) */
-    int64_t in_edges;         /* arcs the round had to read */
-    int64_t out_edges;        /* out-arcs of the changed indices */
-    int32_t bucket;           /* delta-bucket floor (decoded value) or -1 */
-    int32_t pending;          /* entries deferred by the delta filter */
+    int32_t in_count;         /* changed indices the round consumed (its input list) */
+    int32_t out_count;        /* pull rounds: candidates evaluated; 0 for dense and push rounds */
+    int64_t in_edges;         /* out-arcs of the input list */
+    int64_t out_edges;        /* pull rounds: in-arcs of the candidates */
+    int32_t bucket;           /* delta-bucket floor (distance) or -1 */
+    int32_t pending;          /* changed vertices carried to the next round by the delta filter */
 } llp_trace_rec;
 
 typedef struct {
     uint32_t size;              /* sizeof(llp_opts), for ABI evolution; 0 = treat as current */
     uint32_t sched;             /* LLP_SCHED_* */
     uint32_t flags;             /* LLP_* flags */
-    int32_t delta;              /* FIXED: delta-bucket width in decoded units, 0 = none */
-    int64_t max_rounds;         /* watchdog; 0 = problem default (n + 2 rounds for graphs) */
+    int32_t delta;              /* FIXED: delta-bucket width in distance units, 0 = none */
+    int64_t max_rounds;         /* watchdog; 0 = problem default (4n + 64 rounds for graphs, n + 2 for jobs) */
     void* workspace;            /* [device] caller scratch, >= llp_workspace_bytes(); NULL = library-owned */
     size_t workspace_bytes;
     void* stream;               /* hipStream_t */
@@ -110,6 +123,8 @@ typedef struct {
     llp_trace_rec* trace_dev;   /* [device] LLP_TRACE output */
     int64_t trace_cap;
     uint64_t seed;              /* LLP_SCHED_RANDOM seed */
+    const int32_t* plan;        /* [device] LLP_SCHED_SCRIPT: round codes for rounds 1..plan_len */
+    int64_t plan_len;
 } llp_opts;
 
 /* Directed graph as compressed sparse rows, int32 ids, m < 2^31.

@@ -24,7 +24,13 @@ INF32 = 2**31 - 1
 # status codes (llp_status)
 OK, E_ARG, E_INPUT, E_INFEASIBLE, E_OVERFLOW, E_NOT_CONVERGED, E_WORKSPACE, E_HIP, E_CYCLE, E_ABORTED = range(10)
 
-SCHED_PLAIN, SCHED_FIXED, SCHED_LEARNED, SCHED_HYBRID, SCHED_RANDOM = range(5)
+SCHED_PLAIN, SCHED_FIXED, SCHED_LEARNED, SCHED_HYBRID, SCHED_RANDOM, SCHED_SCRIPT = range(6)
+MODE_PULL, MODE_DENSE, MODE_PUSH = 0, 1, 2
+DCLASS_BASE, DCLASS_WIDE, DCLASS_NONE, DCLASS_EXPLICIT = 0, 1, 2, 3
+
+
+def round_code(mode, dclass=DCLASS_NONE):
+    return mode | (dclass << 8)
 PUSH, DENSE, VALIDATE, ASYNC, VERIFY, TRACE, TIMING, JOBS_PULL = (1 << i for i in range(8))
 KIND_SSSP, KIND_BFS, KIND_SM, KIND_JOBS, KIND_KNAPSACK, KIND_TC, KIND_REDUCE, KIND_BATCH = range(1, 9)
 
@@ -66,7 +72,8 @@ class Opts(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("warm_start", ctypes.c_void_p),
                 ("status_dev", ctypes.c_void_p), ("abort_host", ctypes.c_void_p),
                 ("stats", ctypes.POINTER(Stats)), ("chunk", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("trace_dev", ctypes.c_void_p), ("trace_cap", ctypes.c_int64), ("seed", ctypes.c_uint64)]
+                ("trace_dev", ctypes.c_void_p), ("trace_cap", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("plan", ctypes.c_void_p), ("plan_len", ctypes.c_int64)]
 
 
 class Graph(ctypes.Structure):
@@ -165,7 +172,7 @@ def _stream():
 
 
 def make_opts(sched=SCHED_PLAIN, flags=0, delta=0, max_rounds=0, workspace=None, stats=None, chunk=0,
-              block=0, trace=None, seed=0, warm_start=None, abort_host=None, status_dev=None):
+              block=0, trace=None, seed=0, warm_start=None, abort_host=None, status_dev=None, plan=None):
     o = Opts()
     o.size = ctypes.sizeof(Opts)
     o.sched = sched
@@ -190,6 +197,9 @@ def make_opts(sched=SCHED_PLAIN, flags=0, delta=0, max_rounds=0, workspace=None,
         o.trace_dev = trace.data_ptr()
         o.trace_cap = trace.numel() // ctypes.sizeof(TraceRec)
     o.seed = seed
+    if plan is not None:
+        o.plan = plan.data_ptr()
+        o.plan_len = plan.numel()
     return o
 
 

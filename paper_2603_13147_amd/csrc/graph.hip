@@ -43,7 +43,8 @@ struct GCtrl {
     int mode;
     int ovf;
     int verify_changed;
-    int pad0, pad1;
+    int dbase;          // delta base width (2^floor(log2 mean weight), from a sample of the arcs)
+    int carried;        // entries carried by the delta filter this round (traced solves)
     int diag[8];        // first guard event: site, index, bound, context
     long long rounds, cand, edges, adv, xedges;
     SchedHist hist[2];  // scheduler history, double-buffered by round parity
@@ -98,20 +99,48 @@ __global__ void k_graph_init(GArgs a, const int* warm) {
         a.cl0.seg[s] = 0ull;
         a.cl1.seg[s] = 0ull;
         a.wl.seg[s] = 0ull;
+        a.cl0.segmin[s] = LLP_INF;
+        a.cl1.segmin[s] = LLP_INF;
     }
-    if (tid == 0) {
-        GCtrl c;
-        memset(&c, 0, sizeof(c));
-        c.mode = -1;
-        *a.ctrl = c;
-    }
-    if (tid == 0 && !a.jobs) {
-        // CL[0] = {source}: one entry in segment 0
-        int ob = a.out_ptr ? a.out_ptr[a.source] : 0;
-        int od = a.out_ptr ? a.out_ptr[a.source + 1] - ob : 0;
-        if (od > 0) {
-            a.cl0.ent[0] = make_int4(a.source, ob, 0, od);
-            a.cl0.seg[0] = 1ull | ((unsigned long long)(unsigned)od << 32);
+    if (blockIdx.x == 0) {
+        // delta base width: 2^floor(log2 of the mean weight of a stride sample of
+        // the in-arcs) (1 for unit weights)
+        __shared__ long long wsum[4];
+        long long sum = 0;
+        int cnt = 0;
+        if (!a.unit_w && !a.jobs && a.in_w && a.m > 0) {
+            for (int i = threadIdx.x; i < 4096; i += blockDim.x) {
+                long long e = (long long)i * a.m / 4096;
+                sum += a.in_w[e];
+            }
+            cnt = 4096;
+        }
+        sum = wave_sum64(sum);
+        if (lane() == 0) wsum[threadIdx.x >> 6] = sum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            long long t = 0;
+            for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += wsum[k];
+            int base = 1;
+            if (cnt) {
+                long long mean = t / cnt;
+                while ((long long)base * 2 <= mean && base < (1 << 29)) base *= 2;
+            }
+            GCtrl c;
+            memset(&c, 0, sizeof(c));
+            c.mode = -1;
+            c.dbase = base;
+            *a.ctrl = c;
+            if (!a.jobs) {
+                // CL[0] = {source}: one entry in segment 0, distance 0
+                int ob = a.out_ptr ? a.out_ptr[a.source] : 0;
+                int od = a.out_ptr ? a.out_ptr[a.source + 1] - ob : 0;
+                if (od > 0) {
+                    a.cl0.ent[0] = make_int4(a.source, ob, 0, od);
+                    a.cl0.seg[0] = 1ull | ((unsigned long long)(unsigned)od << 32);
+                    a.cl0.segmin[0] = 0;
+                }
+            }
         }
     }
 }
@@ -152,9 +181,13 @@ struct GShared {
     int cnt[MAX_SEG];
     int epre[MAX_SEG + 1];
     int own[GW][64];
-    unsigned long long ctr;
+    unsigned long long ctr;    // appends to the phase's main output list
+    unsigned long long cctr;   // PRE in pull rounds: entries carried into CL[r]
+    int cmin;                  // smallest distance appended to CL[r] by this workgroup
     int tot_edges, tot_count;
-    int mode;
+    int code;
+    int tmp1;
+    int carried;
     int tmp[GW + 1];
 };
 
@@ -174,6 +207,10 @@ __device__ __forceinline__ int jobs_cand(int sp, int dp, bool& ovf) {
     if (c > LLP_INF) { ovf = true; return LLP_INF; }
     return (int)c;
 }
+
+// Distance key of a changed vertex for the delta buckets (its decoded
+// distance; jobs have no buckets and use 0).
+__device__ __forceinline__ int dist_key(const GArgs& a, int g) { return a.jobs ? 0 : LLP_INF - g; }
 
 // Evaluate edges of the iteration: segmented max of candidates per owner,
 // advance owners by atomicMax, append changed vertices to CL.
@@ -195,13 +232,14 @@ __device__ __forceinline__ void eval_body(const GArgs& a, const EdgeCtx& c, int 
     int x = seg_incl_max(cand, seg);
     int nseg = __shfl_down(seg, 1, LLP_WAVE);
     bool tail = c.active && (l == 63 || nseg != seg);
-    bool changed = false;
+    bool changed = false, advanced = false;
     int v = guard(c.own.x, a.n, a.ctrl->diag, 43, c.j, c.own.z);
     if (tail && x > 0) {
         int gv = a.G[v];
         if (x > gv) {
             int old = amax(&a.G[v], x);
-            if (old < x) changed = (amax(&a.cstamp[v], r) < r);
+            advanced = old < x;
+            if (advanced) changed = (amax(&a.cstamp[v], r) < r);
         }
     }
     int ob = 0, od = 0;
@@ -211,13 +249,40 @@ __device__ __forceinline__ void eval_body(const GArgs& a, const EdgeCtx& c, int 
         nadv++;
     }
     append(changed && od > 0, v, ob, od, &sh.ctr, out, &a.ctrl->status);
+    // every advanced vertex is in CL[r] (appended now, earlier this round, or
+    // carried), so its new distance bounds the list's minimum
+    if (out.segmin) wave_min_to_lds(advanced, dist_key(a, x), &sh.cmin);
+}
+
+// Delta buckets: an input entry whose vertex lies at distance >= hi is not
+// expanded (or pushed from) this round but carried into CL[r].  The entry is
+// carried by the lane holding it in the iteration where it starts; every edge
+// lane learns whether its owner is carried.  Returns the owner's flag.
+__device__ __forceinline__ bool carry_step(const GArgs& a, const EdgeCtx& c, int r, long long hi, const ListRef& cl,
+                                           unsigned long long* ctr, GShared& sh) {
+    if (hi <= 0) return false;
+    bool carry = false;
+    int dm = 0;
+    if (c.mine_valid) {
+        int v = guard(c.mine.x, a.n, a.ctrl->diag, 65);
+        dm = LLP_INF - a.G[v];
+        carry = (long long)dm >= hi;
+    }
+    const bool starts = c.mine_valid && c.mine.z >= c.base && c.mine.z < c.limit;
+    const bool put = carry && starts;
+    if (put) amax(&a.cstamp[guard(c.mine.x, a.n, a.ctrl->diag, 66)], r);
+    append(put, c.mine.x, c.mine.y, c.mine.w, ctr, cl, &a.ctrl->status);
+    if (cl.segmin) wave_min_to_lds(put, dm, &sh.cmin);
+    const int k = __popcll(ballot(put));
+    if (lane() == 0 && k && a.trace) atomicAdd(&sh.carried, k);
+    return shfl(carry ? 1 : 0, c.j) != 0;
 }
 
 // Expansion: stamp out-neighbours for round r and append new candidates to WL.
-__device__ __forceinline__ void expand_body(const GArgs& a, const EdgeCtx& c, int r, GShared& sh) {
+__device__ __forceinline__ void expand_body(const GArgs& a, const EdgeCtx& c, int r, GShared& sh, bool skip) {
     bool fresh = false;
     int x = 0, rb = 0, d = 0;
-    if (c.active) {
+    if (c.active && !skip) {
         x = guard(a.out_dst[guard(c.csr, a.m, a.ctrl->diag, 51, c.own.y, c.own.z)], a.n, a.ctrl->diag, 52);
         if (a.stamp[x] < r && amax(&a.stamp[x], r) < r) {
             rb = a.in_ptr[x];
@@ -230,18 +295,17 @@ __device__ __forceinline__ void expand_body(const GArgs& a, const EdgeCtx& c, in
 
 // Push: single-arc partial advance of each out-neighbour (Definition 3).
 __device__ __forceinline__ void push_body(const GArgs& a, const EdgeCtx& c, int r, const ListRef& out,
-                                          GShared& sh, bool& ovf, long long& nadv) {
+                                          GShared& sh, bool& ovf, long long& nadv, bool skip) {
     int umine = c.mine_valid ? guard(c.mine.x, a.n, a.ctrl->diag, 61) : 0;
     int gmine = c.mine_valid ? a.G[umine] : 0;
     int dmine = (c.mine_valid && a.jobs) ? a.vdur[umine] : 0;
     int gu = shfl(gmine, c.j);
     int du = shfl(dmine, c.j);
-    bool changed = false;
-    int x = 0, ob = 0, od = 0;
-    if (c.active) {
+    bool changed = false, advanced = false;
+    int x = 0, ob = 0, od = 0, cand = 0;
+    if (c.active && !skip) {
         int e = guard(c.csr, a.m, a.ctrl->diag, 62, c.own.y, c.own.z);
         x = guard(a.out_dst[e], a.n, a.ctrl->diag, 63);
-        int cand;
         if (a.jobs) {
             cand = jobs_cand(gu, du, ovf);
         } else {
@@ -250,7 +314,8 @@ __device__ __forceinline__ void push_body(const GArgs& a, const EdgeCtx& c, int 
         }
         if (cand > 0 && cand > a.G[x]) {
             int old = amax(&a.G[x], cand);
-            if (old < cand) changed = (amax(&a.cstamp[x], r) < r);
+            advanced = old < cand;
+            if (advanced) changed = (amax(&a.cstamp[x], r) < r);
         }
     }
     if (changed) {
@@ -259,6 +324,7 @@ __device__ __forceinline__ void push_body(const GArgs& a, const EdgeCtx& c, int 
         nadv++;
     }
     append(changed && od > 0, x, ob, od, &sh.ctr, out, &a.ctrl->status);
+    if (out.segmin) wave_min_to_lds(advanced, dist_key(a, cand), &sh.cmin);
 }
 
 __device__ __forceinline__ void wave_range(int total, int& wb, int& we) {
@@ -268,9 +334,22 @@ __device__ __forceinline__ void wave_range(int total, int& wb, int& we) {
     we = (int)((long long)total * (w + 1) / W);
 }
 
-__device__ __forceinline__ void finish_segment(GShared& sh, const ListRef& out) {
-    __syncthreads();
-    if (threadIdx.x == 0) out.seg[blockIdx.x] = sh.ctr;
+__device__ __forceinline__ void publish(const ListRef& out, unsigned long long ctr, int cmin) {
+    out.seg[blockIdx.x] = ctr;
+    if (out.segmin) out.segmin[blockIdx.x] = cmin;
+}
+
+// Delta width of a round code (0: no buckets).
+__device__ __forceinline__ int delta_of(const GArgs& a, int code) {
+    const int mode = code & 3, dc = (code >> 8) & 3;
+    if (a.jobs || mode == MODE_DENSE) return 0;
+    const int base = a.ctrl->dbase > 0 ? a.ctrl->dbase : 1;
+    switch (dc) {
+        case DCLS_BASE: return base;
+        case DCLS_WIDE: return base <= (1 << 27) ? base * 8 : (1 << 30);
+        case DCLS_EXPLICIT: return a.sp.delta;
+        default: return 0;
+    }
 }
 
 // --------------------------------------------------------------- PRE
@@ -290,16 +369,28 @@ __global__ void __launch_bounds__(GB) k_graph_pre(GArgs a, int r) {
     }
     // schedule decision (identical in every workgroup)
     if (threadIdx.x < 64) {
-        int mode = decide_mode(a.sp, a.ctrl->hist[(r + 1) & 1], r, sh.tot_count, sh.tot_edges, a.n, a.m,
+        int code = decide_mode(a.sp, a.ctrl->hist[(r + 1) & 1], r, sh.tot_count, sh.tot_edges, a.n, a.m,
                                force_dense);
-        if (threadIdx.x == 0) sh.mode = mode;
+        if (threadIdx.x == 0) sh.code = code;
     }
-    if (threadIdx.x == 0) sh.ctr = 0ull;
+    if (threadIdx.x == 0) {
+        sh.ctr = 0ull;
+        sh.cctr = 0ull;
+        sh.cmin = LLP_INF;
+        sh.carried = 0;
+    }
     __syncthreads();
-    const int mode = sh.mode;
+    const int code = sh.code;
+    const int mode = code & 3;
+    const int delta = delta_of(a, code);
+    long long hi = 0;   // bucket ceiling (distance), 0 = no buckets
+    if (delta > 0 && in.segmin) {
+        const int dmin = load_segmin(in.segmin, a.nseg, &sh.tmp1);
+        hi = ((long long)dmin / delta) * delta + delta;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         GCtrl* c = a.ctrl;
-        c->mode = mode;
+        c->mode = code;
         c->rounds = r;
         c->adv += sh.tot_count;
         if (mode == MODE_PULL) c->xedges += sh.tot_edges;
@@ -311,12 +402,12 @@ __global__ void __launch_bounds__(GB) k_graph_pre(GArgs a, int r) {
         if (a.trace && r - 1 < a.trace_cap) {
             llp_trace_rec t;
             t.round = r;
-            t.mode = mode;
+            t.mode = code;
             t.in_count = sh.tot_count;
             t.out_count = 0;
             t.in_edges = sh.tot_edges;
             t.out_edges = 0;
-            t.bucket = -1;
+            t.bucket = hi > 0 ? (int)(hi - delta) : -1;
             t.pending = 0;
             a.trace[r - 1] = t;
         }
@@ -330,12 +421,24 @@ __global__ void __launch_bounds__(GB) k_graph_pre(GArgs a, int r) {
     bool ovf = false;
     long long nadv = 0;
     if (mode == MODE_PULL) {
-        for_edges(src, wb, we, own, [&](const EdgeCtx& c) { expand_body(a, c, r, sh); });
-        finish_segment(sh, a.wl);
+        for_edges(src, wb, we, own, [&](const EdgeCtx& c) {
+            bool skip = carry_step(a, c, r, hi, out, &sh.cctr, sh);
+            expand_body(a, c, r, sh, skip);
+        });
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            publish(a.wl, sh.ctr, LLP_INF);
+            publish(out, sh.cctr, sh.cmin);   // MAIN appends after the carried entries
+        }
     } else {
-        for_edges(src, wb, we, own, [&](const EdgeCtx& c) { push_body(a, c, r, out, sh, ovf, nadv); });
-        finish_segment(sh, out);
+        for_edges(src, wb, we, own, [&](const EdgeCtx& c) {
+            bool skip = carry_step(a, c, r, hi, out, &sh.ctr, sh);
+            push_body(a, c, r, out, sh, ovf, nadv, skip);
+        });
+        __syncthreads();
+        if (threadIdx.x == 0) publish(out, sh.ctr, sh.cmin);
     }
+    if (threadIdx.x == 0 && sh.carried) atomicAdd(&a.ctrl->carried, sh.carried);
     if (__any(ovf) && lane() == 0) st_relaxed(&a.ctrl->ovf, 1);
 }
 
@@ -344,10 +447,20 @@ __global__ void __launch_bounds__(GB) k_graph_pre(GArgs a, int r) {
 __global__ void __launch_bounds__(GB) k_graph_main(GArgs a, int r, int verify) {
     __shared__ GShared sh;
     if (!verify && (ld_relaxed(&a.ctrl->done) || ld_relaxed(&a.ctrl->status))) return;
-    const int mode = verify ? MODE_DENSE : a.ctrl->mode;
+    const int code = verify ? MODE_DENSE : a.ctrl->mode;
+    const int mode = code & 3;
+    if (!verify && blockIdx.x == 0 && threadIdx.x == 0 && a.trace && r - 1 < a.trace_cap) {
+        a.trace[r - 1].pending = a.ctrl->carried;
+        a.ctrl->carried = 0;
+    }
     if (mode == MODE_PUSH) return;
     const ListRef out = verify ? a.wl : cl_of(a, r);   // verify writes into WL's storage
-    if (threadIdx.x == 0) sh.ctr = 0ull;
+    if (threadIdx.x == 0) {
+        // pull rounds continue the segment PRE started with carried entries
+        const bool cont = mode == MODE_PULL && !verify;
+        sh.ctr = cont ? out.seg[blockIdx.x] : 0ull;
+        sh.cmin = (cont && out.segmin) ? out.segmin[blockIdx.x] : LLP_INF;
+    }
     int* own = sh.own[threadIdx.x >> 6];
     bool ovf = false;
     long long nadv = 0;
@@ -369,13 +482,18 @@ __global__ void __launch_bounds__(GB) k_graph_main(GArgs a, int r, int verify) {
             a.ctrl->edges += sh.tot_edges;
             a.ctrl->hist[r & 1].wl_count = sh.tot_count;
             a.ctrl->hist[r & 1].wl_edges = sh.tot_edges;
+            if (a.trace && r - 1 < a.trace_cap) {
+                a.trace[r - 1].out_count = sh.tot_count;
+                a.trace[r - 1].out_edges = sh.tot_edges;
+            }
         }
         SegView sv{a.wl.ent, a.wl.cap, a.nseg, sh.cnt, sh.epre, sh.tot_edges, sh.tot_count};
         ListSrc src{sv, a.ctrl->diag};
         wave_range(sh.tot_edges, wb, we);
         for_edges(src, wb, we, own, [&](const EdgeCtx& c) { eval_body(a, c, r, out, sh, ovf, nadv); });
     }
-    finish_segment(sh, out);
+    __syncthreads();
+    if (threadIdx.x == 0) publish(out, sh.ctr, sh.cmin);
     if (__any(ovf) && lane() == 0) st_relaxed(&a.ctrl->ovf, 1);
     if (verify) {
         long long tot = wave_sum64(nadv);
@@ -444,9 +562,13 @@ static size_t graph_ws(int64_t n, int64_t m, GArgs* a, char* base, size_t cap) {
     GCtrl* ctrl = cv.take<GCtrl>(1);
     ListRef lists[3];
     for (int i = 0; i < 3; ++i) {
+        // CL lists hold the entries a delta round carries plus the round's own
+        // appends in one segment: twice the capacity
+        const int cap = i == 0 ? L.cap : 2 * L.cap;
         lists[i].seg = cv.take<unsigned long long>(L.nseg);
-        lists[i].ent = cv.take<int4>((size_t)L.nseg * L.cap);
-        lists[i].cap = L.cap;
+        lists[i].segmin = i == 0 ? nullptr : cv.take<int>(L.nseg);
+        lists[i].ent = cv.take<int4>((size_t)L.nseg * cap);
+        lists[i].cap = cap;
     }
     if (a) {
         a->stamp = stamp;
@@ -487,7 +609,7 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
         return fail(LLP_E_ARG, "out-CSR (out_ptr, out_dst) is required for successor expansion");
     if (o.sched == LLP_SCHED_FIXED && (o.flags & LLP_PUSH) && !bfs && !jobs_dur && !g->out_w)
         return fail(LLP_E_ARG, "push rounds need out_w");
-    if (o.sched > LLP_SCHED_RANDOM) return fail(LLP_E_ARG, "unknown schedule %u", o.sched);
+    if (o.sched > LLP_SCHED_SCRIPT) return fail(LLP_E_ARG, "unknown schedule %u", o.sched);
 
     GArgs a;
     memset(&a, 0, sizeof(a));
@@ -528,7 +650,11 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
     if (o.flags & LLP_VALIDATE) hipLaunchKernelGGL(k_graph_validate, dim3(g1), dim3(256), 0, st, a);
     LLP_HIP(hipGetLastError());
 
-    const int64_t max_rounds = o.max_rounds > 0 ? o.max_rounds : (int64_t)g->n + 2;
+    // watchdog: a DAG of jobs converges within n rounds (the limit is also the
+    // cycle test); delta buckets can add rounds per bucket, hence the wider
+    // graph limit
+    const int64_t max_rounds =
+        o.max_rounds > 0 ? o.max_rounds : (jobs_dur ? (int64_t)g->n + 2 : 4 * (int64_t)g->n + 64);
     GCtrl h;
     memset(&h, 0, sizeof(h));
     int64_t r = 1;

@@ -246,6 +246,7 @@ static size_t jobs_ws(int64_t n, int64_t E, JArgs* a, char* base, size_t cap) {
         lists[i].seg = cv.take<unsigned long long>(L.nseg);
         lists[i].ent = cv.take<int4>((size_t)L.nseg * L.cap);
         lists[i].cap = L.cap;
+        lists[i].segmin = nullptr;
     }
     if (a) {
         a->cnt = cnt;

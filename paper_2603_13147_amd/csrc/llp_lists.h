@@ -23,6 +23,7 @@ namespace llp {
 struct ListRef {
     int4* ent;                    // nb * cap entries
     unsigned long long* seg;      // nb packed totals
+    int* segmin;                  // nb per-segment minimum key (nullable; graph lists: decoded distance)
     int cap;
 };
 
@@ -175,6 +176,8 @@ struct EdgeCtx {
     int csr;       // CSR position of this lane's edge
     int4 mine;     // the window entry held by this lane (valid if lane < avail)
     bool mine_valid;
+    int base;      // virtual edge range of this iteration: [base, limit)
+    int limit;
 };
 
 // Walk virtual edges [wb, we) of src; body(ctx) is called once per iteration
@@ -216,6 +219,8 @@ __device__ inline void for_edges(const Src& src, int wb, int we, int* own_lds, B
         c.csr = c.own.y + (base + l - c.own.z);
         c.mine = e;
         c.mine_valid = valid;
+        c.base = base;
+        c.limit = limit;
         body(c);
         int done = __popcll(ballot(valid && e.z + e.w <= limit));
         cur = src.advance(cur, done);
@@ -246,6 +251,28 @@ __device__ inline void append(bool want, int v, int rb, int deg, unsigned long l
         if (idx < out.cap) out.ent[(long long)blockIdx.x * out.cap + idx] = make_int4(v, rb, off, deg);
         else set_status(status, 7);
     }
+}
+
+// Fold val of the lanes with want into the workgroup minimum *lds_min (one
+// LDS atomic per wave).
+__device__ inline void wave_min_to_lds(bool want, int val, int* lds_min) {
+    int x = want ? val : 0x7fffffff;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x = min(x, __shfl_xor(x, d, LLP_WAVE));
+    if (lane() == 0 && x != 0x7fffffff) atomicMin(lds_min, x);
+}
+
+// Minimum of seg_min[0..nseg) over the workgroup (every thread gets it).
+__device__ inline int load_segmin(const int* seg_min, int nseg, int* lds_tmp1) {
+    int x = 0x7fffffff;
+    for (int i = threadIdx.x; i < nseg; i += blockDim.x) x = min(x, seg_min[i]);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x = min(x, __shfl_xor(x, d, LLP_WAVE));
+    if (threadIdx.x == 0) *lds_tmp1 = 0x7fffffff;
+    __syncthreads();
+    if (lane() == 0) atomicMin(lds_tmp1, x);
+    __syncthreads();
+    return *lds_tmp1;
 }
 
 }  // namespace llp

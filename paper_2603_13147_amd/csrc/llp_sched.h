@@ -36,7 +36,13 @@ struct SchedParams {
     unsigned long long seed;
     const unsigned short* mlp;   // bf16 parameter block (LLP_MLP_PARAMS), device
     float dense_frac;            // HYBRID: dense when changed out-arcs exceed this fraction of m
+    const int* plan;             // SCRIPT: round codes (device)
+    long long plan_len;
 };
+
+enum { DCLS_BASE = 0, DCLS_WIDE = 1, DCLS_NONE = 2, DCLS_EXPLICIT = 3 };
+
+__device__ __forceinline__ int round_code(int mode, int dcls) { return mode | (dcls << 8); }
 
 int sched_params(const llp_opts& o, bool can_push, SchedParams* sp);
 const unsigned short* learned_weights_device();
@@ -102,34 +108,49 @@ __device__ __forceinline__ unsigned long long mix64d(unsigned long long z) {
     return z ^ (z >> 31);
 }
 
-// Mode of round r: 0 pull (worklist), 1 dense pull, 2 push.  Call from a
-// whole wave; the result is wave-uniform.
+// Code of round r: mode (bits 0-1: 0 pull over the worklist, 1 dense pull,
+// 2 push) and delta class (bits 8-9).  Call from a whole wave; the result is
+// wave-uniform, and identical in every workgroup (same inputs).
 __device__ inline int decide_mode(const SchedParams& sp, const SchedHist& h, int r, int cl_count, int cl_edges,
                                   int n, int m, int force_dense) {
-    if (force_dense) return 1;
+    if (force_dense) return round_code(1, DCLS_NONE);
     switch (sp.sched) {
-        case LLP_SCHED_FIXED:
-            if (sp.flags & LLP_DENSE) return 1;
-            if ((sp.flags & LLP_PUSH) && sp.can_push) return 2;
-            return 0;
+        case LLP_SCHED_FIXED: {
+            const int dc = sp.delta > 0 ? DCLS_EXPLICIT : DCLS_NONE;
+            if (sp.flags & LLP_DENSE) return round_code(1, dc);
+            if ((sp.flags & LLP_PUSH) && sp.can_push) return round_code(2, dc);
+            return round_code(0, dc);
+        }
         case LLP_SCHED_HYBRID:
-            return (float)cl_edges > sp.dense_frac * (float)m ? 1 : 0;
+            return round_code((float)cl_edges > sp.dense_frac * (float)m ? 1 : 0, DCLS_NONE);
         case LLP_SCHED_RANDOM: {
             unsigned long long z = mix64d(sp.seed * 0x9E3779B97F4A7C15ull + (unsigned long long)r);
             int k = (int)(z % (unsigned long long)(sp.can_push ? 3 : 2));
-            return k;
+            int dc = (int)((z >> 32) % 3ull);
+            return round_code(k, dc);
+        }
+        case LLP_SCHED_SCRIPT: {
+            if (!sp.plan || (long long)r > sp.plan_len) return round_code(0, DCLS_NONE);
+            int c = sp.plan[r - 1];
+            int mode = c & 3, dc = (c >> 8) & 3;
+            if (mode == 3 || (mode == 2 && !sp.can_push)) mode = 0;
+            if (dc == DCLS_EXPLICIT && sp.delta <= 0) dc = DCLS_NONE;
+            return round_code(mode, dc);
         }
         case LLP_SCHED_LEARNED: {
-            if (!sp.mlp) return 0;
+            if (!sp.mlp) return round_code(0, DCLS_NONE);
             float f[12], o[5];
             round_features(f, r, cl_count, cl_edges, n, m, h);
             mlp_forward_wave(sp.mlp, f, o);
-            if (o[0] > 0.f && sp.can_push) return 2;
-            if (o[1] > 0.f) return 1;
-            return 0;
+            int dc = DCLS_BASE;
+            if (o[3] > o[2]) dc = DCLS_WIDE;
+            if (o[4] > fmaxf(o[2], o[3])) dc = DCLS_NONE;
+            if (o[0] > 0.f && sp.can_push) return round_code(2, dc);
+            if (o[1] > 0.f) return round_code(1, dc);
+            return round_code(0, dc);
         }
         default:
-            return 0;
+            return round_code(0, DCLS_NONE);
     }
 }
 

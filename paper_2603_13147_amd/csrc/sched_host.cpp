@@ -39,6 +39,12 @@ int sched_params(const llp_opts& o, bool can_push, SchedParams* sp) {
     sp->can_push = can_push ? 1 : 0;
     sp->seed = o.seed;
     sp->dense_frac = 0.05f;
+    if (o.sched == LLP_SCHED_SCRIPT) {
+        if (o.plan_len < 0 || (o.plan_len > 0 && !o.plan)) return fail(LLP_E_ARG, "SCRIPT needs plan and plan_len");
+        sp->plan = o.plan;
+        sp->plan_len = o.plan_len;
+    }
+    if (o.delta < 0) return fail(LLP_E_ARG, "delta must be >= 0");
     if (o.sched == LLP_SCHED_LEARNED) {
         sp->mlp = learned_weights_device();
         if (!sp->mlp) return fail(LLP_E_ARG, "LLP_SCHED_LEARNED needs llp_sched_set_weights() first");

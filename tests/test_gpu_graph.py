@@ -20,6 +20,8 @@ SCHEDS = [
     dict(sched=llp.SCHED_HYBRID),
     dict(sched=llp.SCHED_RANDOM, seed=1),
     dict(sched=llp.SCHED_RANDOM, seed=7),
+    dict(sched=llp.SCHED_FIXED, delta=40),
+    dict(sched=llp.SCHED_FIXED, flags=llp.PUSH, delta=7),
 ]
 
 
@@ -46,7 +48,7 @@ def test_worked_example():
         assert run(llp.sssp, dg, 0, **kw).tolist() == [0, 2, 5, 3], kw
 
 
-@pytest.mark.parametrize("kw", SCHEDS, ids=lambda k: f"s{k['sched']}f{k.get('flags', 0)}r{k.get('seed', 0)}")
+@pytest.mark.parametrize("kw", SCHEDS, ids=lambda k: f"s{k['sched']}f{k.get('flags', 0)}r{k.get('seed', 0)}d{k.get('delta', 0)}")
 def test_uniform_4096_all_schedules(kw):
     """The small configuration: n=4096, 32768 uniform arcs + Hamiltonian cycle, w U[1,100], source 0."""
     g = llpgen.uniform_graph(4096, 32768, 1, 100, seed=1)
@@ -206,3 +208,51 @@ def test_verify_and_stats_and_trace():
     rec = np.frombuffer(trace.cpu().numpy().tobytes(), dtype=llp.TRACE_DTYPE)[: st.rounds]
     assert rec["round"].tolist() == list(range(1, st.rounds + 1))
     assert rec["in_count"][0] == 1          # round 1 expands the source alone
+
+
+DELTA_SCHEDS = [dict(sched=llp.SCHED_FIXED, delta=d) for d in (1, 16, 64, 255, 4000)] + [
+    dict(sched=llp.SCHED_FIXED, flags=llp.PUSH, delta=32),
+    dict(sched=llp.SCHED_RANDOM, seed=3), dict(sched=llp.SCHED_RANDOM, seed=4),
+    dict(sched=llp.SCHED_RANDOM, seed=5),
+]
+
+
+@pytest.mark.parametrize("which", ["rmat14", "grid64", "uniform4096"])
+def test_delta_buckets_and_scripts(which):
+    """Delta-bucket rounds (every width, pull and push) and scripted per-round
+    codes reach the oracle's fixpoint bit for bit."""
+    if which == "rmat14":
+        g = llpgen.rmat_graph(14, seed=11)
+    elif which == "grid64":
+        g = llpgen.grid_graph(64, 64, seed=12)
+    else:
+        g = llpgen.uniform_graph(4096, 32768, 1, 100, seed=13)
+    s = llpgen.max_outdeg_source(g)
+    want = oracle.sssp(g.n, g.src, g.dst, g.w, s, bag=True)
+    wantb = oracle.bfs(g.n, g.src, g.dst, s, bag=True)
+    _, dg = dev_graph(g)
+    for kw in DELTA_SCHEDS:
+        assert np.array_equal(run(llp.sssp, dg, s, **kw), want), kw
+        assert np.array_equal(run(llp.bfs, dg, s, **kw), wantb), kw
+    rng = np.random.default_rng(5)
+    for t in range(6):
+        codes = [llp.round_code(int(rng.integers(0, 3)), int(rng.integers(0, 3))) for _ in range(int(rng.integers(1, 60)))]
+        plan = torch.tensor(codes, dtype=torch.int32, device="cuda")
+        assert np.array_equal(run(llp.sssp, dg, s, sched=llp.SCHED_SCRIPT, plan=plan), want), codes
+        assert np.array_equal(run(llp.bfs, dg, s, sched=llp.SCHED_SCRIPT, plan=plan), wantb), codes
+
+
+def test_trace_records_delta_rounds():
+    g = llpgen.rmat_graph(12, seed=4)
+    s = llpgen.max_outdeg_source(g)
+    _, dg = dev_graph(g)
+    trace = torch.zeros(4096 * 40, dtype=torch.uint8, device="cuda")
+    st = llp.Stats()
+    d = run(llp.sssp, dg, s, sched=llp.SCHED_FIXED, delta=64, flags=llp.TRACE, trace=trace, stats=st)
+    assert np.array_equal(d, oracle.sssp(g.n, g.src, g.dst, g.w, s))
+    rec = np.frombuffer(trace.cpu().numpy().tobytes(), llp.TRACE_DTYPE)[: st.rounds]
+    assert np.array_equal(rec["round"], np.arange(1, st.rounds + 1))
+    assert np.all((rec["mode"] >> 8) == llp.DCLASS_EXPLICIT)
+    assert np.all(rec["bucket"] % 64 == 0) and np.all(rec["bucket"] >= 0)
+    assert rec["pending"].sum() > 0                      # some vertices waited for their bucket
+    assert rec["out_count"].sum() > 0                    # pull rounds evaluated candidates
