@@ -84,13 +84,17 @@ typedef enum {
 /* Per-solve counters (host struct, filled when opts->stats != NULL). */
 typedef struct {
     int64_t rounds;           /* sweep rounds executed */
-    int64_t candidates;       /* indices evaluated by pull rounds (+ indices pushed by push rounds) */
-    int64_t edges_inspected;  /* in-arcs read by pull rounds + out-arcs read by push rounds */
-    int64_t advances;         /* indices advanced (entries of the changed lists) */
+    int64_t candidates;       /* indices evaluated by pull rounds (every index in a dense round) */
+    int64_t edges_inspected;  /* in-arcs read by pull rounds */
+    int64_t advances;         /* entries of the changed lists consumed (indices advanced) */
     int64_t expand_edges;     /* out-arcs read by successor expansion */
-    int64_t eval_launches;    /* launches of the evaluation kernel (LLP_TIMING) */
+    int64_t eval_launches;    /* launches of the evaluation (MAIN) kernel (LLP_TIMING) */
     float device_ms;          /* whole solve on the stream (LLP_TIMING) */
-    float kernel_ms;          /* summed duration of the evaluation kernel launches (LLP_TIMING) */
+    float kernel_ms;          /* summed duration of the evaluation (MAIN) kernel launches (LLP_TIMING) */
+    int64_t push_edges;       /* out-arcs read by push rounds */
+    int64_t pre_launches;     /* launches of the expansion / push (PRE) kernel (LLP_TIMING) */
+    float pre_ms;             /* summed duration of the PRE kernel launches (LLP_TIMING) */
+    float pad;
 } llp_stats;
 
 /* One record per round when LLP_TRACE is set (device buffer of trace_cap records). */

@@ -48,7 +48,9 @@ class Stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("edges_inspected", ctypes.c_int64), ("advances", ctypes.c_int64),
                 ("expand_edges", ctypes.c_int64), ("eval_launches", ctypes.c_int64),
-                ("device_ms", ctypes.c_float), ("kernel_ms", ctypes.c_float)]
+                ("device_ms", ctypes.c_float), ("kernel_ms", ctypes.c_float),
+                ("push_edges", ctypes.c_int64), ("pre_launches", ctypes.c_int64),
+                ("pre_ms", ctypes.c_float), ("pad", ctypes.c_float)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -430,3 +432,67 @@ def reduce_sum(x, ws=None, **kw):
     o = make_opts(workspace=ws, **kw)
     _check(lib().llp_solve_reduce(x.numel(), _ptr(x), _ptr(out), ctypes.byref(o)))
     return int(out.cpu().numpy().view(np.uint64)[0])
+
+
+# ---------------------------------------------------------------- learned scheduler
+def set_sched_weights(params):
+    """Load FP32 master weights (LLP_MLP_PARAMS floats) for LLP_SCHED_LEARNED on the current device."""
+    p = np.ascontiguousarray(np.asarray(params, np.float32).ravel())
+    if p.shape[0] != MLP_PARAMS:
+        raise LLPError(E_ARG, f"expected {MLP_PARAMS} parameters, got {p.shape[0]}")
+    _torch()
+    _check(lib().llp_sched_set_weights(p.ctypes.data_as(ctypes.c_void_p)))
+
+
+def default_sched_weights_path():
+    return os.path.join(_HERE, "sched_weights.npy")
+
+
+def mlp_forward(params, x):
+    """(logits[B,5] fp32, act[B,128] bf16 bits as int16) for device tensors params[5317], x[B,12]."""
+    torch = _torch()
+    B = int(x.shape[0])
+    logits = torch.empty((B, MLP_OUT), dtype=torch.float32, device="cuda")
+    act = torch.empty((B, 2 * MLP_HID), dtype=torch.int16, device="cuda")
+    _check(lib().llp_mlp_forward(B, _ptr(params), _ptr(x), _ptr(logits), _ptr(act), _stream()))
+    return logits, act
+
+
+def mlp_loss(logits, labels):
+    """(loss[1] fp32, dlogits[B,5]) for round-code labels[B] int32."""
+    torch = _torch()
+    B = int(logits.shape[0])
+    dl = torch.empty_like(logits)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    _check(lib().llp_mlp_loss(B, _ptr(logits), _ptr(labels), _ptr(dl), _ptr(loss), _stream()))
+    return loss, dl
+
+
+def mlp_backward(params, x, act, dlogits, grad):
+    """grad += d loss / d params (grad: fp32[5317] device tensor)."""
+    _torch()
+    B = int(x.shape[0])
+    _check(lib().llp_mlp_backward(B, _ptr(params), _ptr(x), _ptr(act), _ptr(dlogits), _ptr(grad), _stream()))
+
+
+def mlp_adam(grad, params, m1, m2, step, lr):
+    _torch()
+    _check(lib().llp_mlp_adam(_ptr(grad), _ptr(params), _ptr(m1), _ptr(m2), int(step), ctypes.c_float(lr),
+                              _stream()))
+
+
+def trace_features(trace, rounds, n, m):
+    """features[rounds,12] fp32 (device) of a trace buffer filled by LLP_TRACE."""
+    torch = _torch()
+    F = torch.empty((max(rounds, 1), MLP_IN), dtype=torch.float32, device="cuda")
+    _check(lib().llp_trace_features(int(rounds), _ptr(trace), int(n), int(m), _ptr(F), _stream()))
+    return F[:rounds]
+
+
+def trace_buffer(cap):
+    torch = _torch()
+    return torch.zeros(cap * ctypes.sizeof(TraceRec), dtype=torch.uint8, device="cuda")
+
+
+def trace_records(trace, rounds):
+    return np.frombuffer(trace.cpu().numpy().tobytes(), TRACE_DTYPE)[:rounds].copy()

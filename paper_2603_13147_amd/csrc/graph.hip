@@ -46,7 +46,7 @@ struct GCtrl {
     int dbase;          // delta base width (2^floor(log2 mean weight), from a sample of the arcs)
     int carried;        // entries carried by the delta filter this round (traced solves)
     int diag[8];        // first guard event: site, index, bound, context
-    long long rounds, cand, edges, adv, xedges;
+    long long rounds, cand, edges, adv, xedges, pedges;
     SchedHist hist[2];  // scheduler history, double-buffered by round parity
 };
 
@@ -394,10 +394,7 @@ __global__ void __launch_bounds__(GB) k_graph_pre(GArgs a, int r) {
         c->rounds = r;
         c->adv += sh.tot_count;
         if (mode == MODE_PULL) c->xedges += sh.tot_edges;
-        if (mode == MODE_PUSH) {
-            c->edges += sh.tot_edges;
-            c->cand += sh.tot_count;
-        }
+        if (mode == MODE_PUSH) c->pedges += sh.tot_edges;
         hist_push(c->hist[r & 1], c->hist[(r + 1) & 1], r, mode, sh.tot_count, sh.tot_edges);
         if (a.trace && r - 1 < a.trace_cap) {
             llp_trace_rec t;
@@ -661,9 +658,21 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
     int batch = 4;
     int status = LLP_OK;
     std::vector<hipEvent_t> evs;     // LLP_TIMING: one pair around each MAIN launch
+    std::vector<hipEvent_t> pevs;    // and around each PRE launch
     for (;;) {
         for (int i = 0; i < batch && r <= max_rounds; ++i, ++r) {
-            hipLaunchKernelGGL(k_graph_pre, dim3(a.nseg), dim3(GB), 0, st, a, (int)r);
+            if (timing) {
+                hipEvent_t p0, p1;
+                LLP_HIP(hipEventCreate(&p0));
+                LLP_HIP(hipEventCreate(&p1));
+                LLP_HIP(hipEventRecord(p0, st));
+                hipLaunchKernelGGL(k_graph_pre, dim3(a.nseg), dim3(GB), 0, st, a, (int)r);
+                LLP_HIP(hipEventRecord(p1, st));
+                pevs.push_back(p0);
+                pevs.push_back(p1);
+            } else {
+                hipLaunchKernelGGL(k_graph_pre, dim3(a.nseg), dim3(GB), 0, st, a, (int)r);
+            }
             if (timing) {
                 hipEvent_t e0, e1;
                 LLP_HIP(hipEventCreate(&e0));
@@ -696,12 +705,15 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
     s = readback(st, a.ctrl, &h, sizeof(h));
     if (s) return s;
     if (o.stats) {
+        memset(o.stats, 0, sizeof(*o.stats));
         o.stats->rounds = h.rounds;
         o.stats->candidates = h.cand;
         o.stats->edges_inspected = h.edges;
         o.stats->advances = h.adv;
         o.stats->expand_edges = h.xedges;
         o.stats->eval_launches = (int64_t)(evs.size() / 2);
+        o.stats->pre_launches = (int64_t)(pevs.size() / 2);
+        o.stats->push_edges = h.pedges;
         if (timing) {
             float ms = 0.f, kms = 0.f;
             LLP_HIP(hipEventElapsedTime(&ms, ev0, ev1));
@@ -710,11 +722,19 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
                 LLP_HIP(hipEventElapsedTime(&t, evs[i], evs[i + 1]));
                 kms += t;
             }
+            float pms = 0.f;
+            for (size_t i = 0; i + 1 < pevs.size(); i += 2) {
+                float t = 0.f;
+                LLP_HIP(hipEventElapsedTime(&t, pevs[i], pevs[i + 1]));
+                pms += t;
+            }
             o.stats->device_ms = ms;
             o.stats->kernel_ms = kms;
+            o.stats->pre_ms = pms;
         }
     }
     for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    for (hipEvent_t e : pevs) (void)hipEventDestroy(e);
     if (timing) {
         (void)hipEventDestroy(ev0);
         (void)hipEventDestroy(ev1);

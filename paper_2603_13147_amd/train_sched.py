@@ -1,0 +1,172 @@
+"""Train the learned per-round scheduler on the GPU from the sweep's own traces.
+
+For each training graph the plain schedule is run once with LLP_TRACE; the
+round features come from the trace (llp_trace_features, the same function the
+sweep evaluates when it decides a round).  A sample of rounds is labelled by
+measurement: for round r and every candidate round code a (push / pull /
+dense x delta class), the solve is re-run with the script schedule
+(plain for rounds < r, a for rounds r .. r+h-1, plain afterwards) and timed
+on the device; the label is the code with the smallest median time.  The
+network is then fitted with the library's own forward, loss, backward and
+Adam kernels (full batch), and the FP32 master weights are saved as .npy.
+
+Usage (on a machine with an MI355X):
+    python -m paper_2603_13147_amd.train_sched --out sched_weights.npy
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import llpgen  # noqa: E402
+import paper_2603_13147_amd as llp  # noqa: E402
+
+PLAIN = llp.round_code(llp.MODE_PULL, llp.DCLASS_NONE)
+ACTIONS = [llp.round_code(m, d) for m in (llp.MODE_PULL, llp.MODE_DENSE, llp.MODE_PUSH)
+           for d in (llp.DCLASS_BASE, llp.DCLASS_WIDE, llp.DCLASS_NONE)
+           if not (m == llp.MODE_DENSE and d != llp.DCLASS_NONE)]
+
+
+def init_params(seed=0):
+    """He-uniform weights, zero biases (float32[LLP_MLP_PARAMS])."""
+    rng = np.random.default_rng(seed)
+    shapes = [(64, 12), (64,), (64, 64), (64,), (5, 64), (5,)]
+    parts = []
+    for s in shapes:
+        if len(s) == 2:
+            lim = np.sqrt(6.0 / s[1])
+            parts.append(rng.uniform(-lim, lim, size=s).ravel())
+        else:
+            parts.append(np.zeros(s))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def solve_fn(kind):
+    return llp.sssp if kind == "sssp" else llp.bfs
+
+
+def timed(fn, dg, source, ws, out, reps, **kw):
+    import torch
+    ts = []
+    flags = kw.pop("flags", 0) | llp.TIMING
+    for _ in range(reps):
+        st = llp.Stats()
+        fn(dg, source, out=out, ws=ws, stats=st, flags=flags, **kw)
+        ts.append(st.device_ms)
+    torch.cuda.synchronize()
+    return float(np.median(ts))
+
+
+def label_graph(name, g, kinds, max_rows, horizon, reps, log):
+    """Features and labels of sampled rounds of the plain sweep on g."""
+    import torch
+    s = llpgen.max_outdeg_source(g)
+    csr = llpgen.CSRGraph(g, weighted=True, out_weights=True)
+    dg = llp.DeviceGraph(csr)
+    ws = llp.workspace(llp.KIND_SSSP, g.n, g.m)
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    X, Y = [], []
+    for kind in kinds:
+        fn = solve_fn(kind)
+        cap = 4 * g.n + 64
+        trace = llp.trace_buffer(min(cap, 1 << 20))
+        st = llp.Stats()
+        fn(dg, s, out=out, ws=ws, stats=st, flags=llp.TRACE, trace=trace)
+        R = int(st.rounds)
+        F = llp.trace_features(trace, R, g.n, g.m).cpu().numpy()
+        rows = np.arange(1, R + 1) if R <= max_rows else np.unique(np.linspace(1, R, max_rows).astype(int))
+        base = timed(fn, dg, s, ws, out, reps)
+        t0 = time.time()
+        counts = {}
+        for r in rows:
+            costs = []
+            for a in ACTIONS:
+                plan = torch.tensor([PLAIN] * (int(r) - 1) + [a] * horizon, dtype=torch.int32, device="cuda")
+                costs.append(timed(fn, dg, s, ws, out, reps, sched=llp.SCHED_SCRIPT, plan=plan))
+            best = ACTIONS[int(np.argmin(costs))]
+            X.append(F[r - 1])
+            Y.append(best)
+            counts[best] = counts.get(best, 0) + 1
+        log(f"{name} {kind}: n={g.n} m={g.m} rounds={R} plain={base:.3f} ms labelled={len(rows)} "
+            f"in {time.time() - t0:.1f}s labels={counts}")
+    return X, Y
+
+
+def fit(X, Y, steps, lr, seed, log):
+    import torch
+    x = torch.tensor(np.asarray(X, np.float32), device="cuda")
+    y = torch.tensor(np.asarray(Y, np.int32), device="cuda")
+    p = torch.tensor(init_params(seed), device="cuda")
+    m1 = torch.zeros_like(p)
+    m2 = torch.zeros_like(p)
+    grad = torch.zeros_like(p)
+    for step in range(1, steps + 1):
+        logits, act = llp.mlp_forward(p, x)
+        loss, dl = llp.mlp_loss(logits, y)
+        grad.zero_()
+        llp.mlp_backward(p, x, act, dl, grad)
+        llp.mlp_adam(grad, p, m1, m2, step, lr)
+        if step % 500 == 0 or step == 1:
+            log(f"step {step} loss {float(loss.item()):.4f}")
+    logits, _ = llp.mlp_forward(p, x)
+    z = logits.cpu().numpy()
+    pred = np.where((z[:, 0] > 0), 2, np.where(z[:, 1] > 0, 1, 0)) | (np.argmax(z[:, 2:], axis=1) << 8)
+    acc = float(np.mean(pred == np.asarray(Y)))
+    log(f"training accuracy {acc:.3f} on {len(Y)} rounds")
+    return p.cpu().numpy(), acc
+
+
+def training_graphs(quick=False):
+    """(name, EdgeList) of the training set: R-MAT scales 18-20 and 2048^2 grids."""
+    out = []
+    scales = [(14, 100)] if quick else [(18, 100), (18, 101), (19, 102), (19, 103), (20, 104), (20, 105)]
+    for sc, seed in scales:
+        out.append((f"rmat{sc}-s{seed}", llpgen.rmat_graph(sc, seed=seed), ("sssp", "bfs")))
+    grids = [(64, 100)] if quick else [(2048, 106)]
+    for side, seed in grids:
+        out.append((f"grid{side}-s{seed}", llpgen.grid_graph(side, side, seed=seed), ("sssp",)))
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--rows", type=int, default=40, help="rounds labelled per trace")
+    ap.add_argument("--grid-rows", type=int, default=24)
+    ap.add_argument("--horizon", type=int, default=4)
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--quick", action="store_true", help="tiny graphs (smoke test of the pipeline)")
+    a = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, flush=True)
+
+    X, Y = [], []
+    for name, g, kinds in training_graphs(a.quick):
+        rows = a.grid_rows if name.startswith("grid") else a.rows
+        reps = 2 if name.startswith("grid") else a.reps
+        x, y = label_graph(name, g, kinds, rows, a.horizon, reps, log)
+        X += x
+        Y += y
+    p, acc = fit(X, Y, a.steps, a.lr, a.seed, log)
+    np.save(a.out, p.astype(np.float32))
+    with open(os.path.splitext(a.out)[0] + ".json", "w") as f:
+        json.dump({"rows": len(Y), "train_accuracy": acc, "actions": ACTIONS,
+                   "labels": {str(k): int(v) for k, v in zip(*np.unique(Y, return_counts=True))}}, f)
+    log(f"saved {a.out}")
+
+
+if __name__ == "__main__":
+    main()

@@ -11,11 +11,6 @@ from conftest import ROOT
 HEADER = os.path.join(ROOT, "include", "llp.h")
 LIB = os.path.join(ROOT, "paper_2603_13147_amd", "libllp.so")
 
-# Entry points declared in the header whose plugins are still being written;
-# this set only shrinks.
-NOT_YET_BUILT = {
-    "llp_mlp_forward", "llp_mlp_loss", "llp_mlp_backward", "llp_mlp_adam", "llp_trace_features",
-}
 
 
 def declared():
@@ -36,9 +31,7 @@ def test_header_declares_the_solvers():
 def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(LIB)
     missing = [n for n in declared() if not hasattr(lib, n)]
-    assert set(missing) <= NOT_YET_BUILT, sorted(set(missing) - NOT_YET_BUILT)
-    # a symbol that has landed must leave the not-yet-built list
-    assert not [n for n in NOT_YET_BUILT if hasattr(lib, n)]
+    assert not missing, missing
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libllp.so not built")

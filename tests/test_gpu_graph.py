@@ -208,6 +208,12 @@ def test_verify_and_stats_and_trace():
     rec = np.frombuffer(trace.cpu().numpy().tobytes(), dtype=llp.TRACE_DTYPE)[: st.rounds]
     assert rec["round"].tolist() == list(range(1, st.rounds + 1))
     assert rec["in_count"][0] == 1          # round 1 expands the source alone
+    assert st.pre_launches == st.eval_launches and st.pre_ms > 0 and st.kernel_ms > 0
+    assert st.push_edges == 0 and st.expand_edges > 0
+    stp = llp.Stats()
+    got = run(llp.sssp, dg, 0, sched=llp.SCHED_FIXED, flags=llp.PUSH | llp.TIMING, stats=stp)
+    assert np.array_equal(got, oracle.sssp(g.n, g.src, g.dst, g.w, 0))
+    assert stp.push_edges >= g.m // 4 and stp.edges_inspected == 0 and stp.pre_ms > 0
 
 
 DELTA_SCHEDS = [dict(sched=llp.SCHED_FIXED, delta=d) for d in (1, 16, 64, 255, 4000)] + [
