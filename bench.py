@@ -1,19 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark of the LLP sweep on one MI355X.
 
-Workload: R-MAT scale 22 (4,194,304 vertices, 67,108,864 R-MAT arcs with
-(a, b, c, d) = (0.57, 0.19, 0.19, 0.05), seeded vertex relabelling, plus the
-Hamiltonian cycle 0 -> 1 -> ... -> n-1 -> 0: m = 71,303,168 arcs), int32
+Headline workload: R-MAT scale 22 (4,194,304 vertices, 67,108,864 R-MAT arcs
+with (a, b, c, d) = (0.57, 0.19, 0.19, 0.05), seeded vertex relabelling, plus
+the Hamiltonian cycle 0 -> 1 -> ... -> n-1 -> 0: m = 71,303,168 arcs), int32
 weights U[1, 255] for SSSP and unit weights for BFS, source = the vertex of
 highest out-degree (smallest id on ties).  Synthetic, seeded (seed 22).
 
 One step = one SSSP solve + one BFS solve to the LLP fixpoint on that graph,
-inputs resident in HBM.  value = 2 m / step time (GTEPS, every input arc
-counted once per solve).  The JSON line also carries each solve's GTEPS, the
-roofline of the evaluation kernel (the dominant kernel: pull evaluation of the
-candidate worklist), measured with HIP events around each of its launches on
-the solve's stream, and the CPU oracle timed on the host on one SSSP solve of
-the same graph.
+inputs resident in HBM, with the headline schedule (the learned scheduler
+when its weights are present, else the plain schedule).  value = 2 m / step
+time (GTEPS, every input arc counted once per solve).
+
+The JSON line also carries
+  - each solve's GTEPS, rounds and work counters;
+  - the learned-vs-plain comparison on the same graph (and the other fixed
+    schedules), plus the held-out evaluation graphs of the learned scheduler
+    (R-MAT 22 seed 900, 4096^2 grid seed 900) when --heldout is given;
+  - the batched persistent solve: 4096 knapsack + 4096 small SSSP instances
+    in one hipGraph-replayed launch (solves/s);
+  - the roofline of the dominant kernel of the headline step (the kernel with
+    the most device time: PRE = expansion / push, MAIN = pull evaluation),
+    from HIP events around each of its launches on the solve's stream;
+  - the CPU oracle timed on the host on one SSSP solve of the same graph.
 """
 from __future__ import annotations
 
@@ -37,13 +46,65 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--scale", type=int, default=22)
-    p.add_argument("--sched", default="plain", choices=["plain", "hybrid", "dense", "push", "learned"])
+    p.add_argument("--sched", default="auto", choices=["auto", "plain", "hybrid", "dense", "push", "learned"])
     p.add_argument("--delta", type=int, default=0,
                    help="delta-bucket width for the fixed schedules (plain becomes fixed pull)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-compare", action="store_true", help="skip the schedule comparison")
+    p.add_argument("--no-batch", action="store_true", help="skip the batched-solve measurement")
+    p.add_argument("--heldout", action="store_true", help="also time the learned scheduler's held-out graphs")
     p.add_argument("--profile-steps", type=int, default=0,
-                   help="run only this many steps, no baseline (for rocprofv3 runs)")
+                   help="run only this many headline steps, nothing else (for rocprofv3 runs)")
     return p.parse_args()
+
+
+def sched_kw(llp, name, delta=0):
+    kw = {"plain": dict(sched=llp.SCHED_PLAIN), "hybrid": dict(sched=llp.SCHED_HYBRID),
+          "dense": dict(sched=llp.SCHED_FIXED, flags=llp.DENSE),
+          "push": dict(sched=llp.SCHED_FIXED, flags=llp.PUSH),
+          "learned": dict(sched=llp.SCHED_LEARNED)}[name]
+    if delta > 0:
+        if kw["sched"] == llp.SCHED_PLAIN:
+            kw = dict(sched=llp.SCHED_FIXED)
+        kw["delta"] = delta
+    return kw
+
+
+def run_step(llp, dg, src, ws, dist, lev, kw, timing):
+    s1, s2 = llp.Stats(), llp.Stats()
+    k = dict(kw)
+    k["flags"] = k.get("flags", 0) | (llp.TIMING if timing else 0)
+    llp.sssp(dg, src, out=dist, ws=ws, stats=s1, **k)
+    llp.bfs(dg, src, out=lev, ws=ws, stats=s2, **k)
+    return s1, s2
+
+
+def kernel_bytes(s, weighted):
+    """Algorithmic bytes of the MAIN (pull evaluation) and PRE (expansion / push)
+    kernels of one solve: MAIN reads per in-arc the source id, the weight
+    (SSSP) and the gathered state (12 / 8 B) and 16 B per candidate entry; PRE
+    reads 16 B per changed entry, per expansion arc the target id and its stamp
+    (8 B), per push arc the target id, weight and state (12 / 8 B)."""
+    arc = 12 if weighted else 8
+    main = arc * s.edges_inspected + 16 * s.candidates
+    pre = 16 * s.advances + 8 * s.expand_edges + arc * s.push_edges
+    return main, pre
+
+
+def time_steps(llp, dg, src, ws, dist, lev, kw, steps, warm, torch):
+    """Wall time per step over `steps` steps without per-launch events, then
+    the same number of steps with LLP_TIMING for the kernel counters."""
+    for _ in range(warm):
+        run_step(llp, dg, src, ws, dist, lev, kw, False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        run_step(llp, dg, src, ws, dist, lev, kw, False)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t1) / steps
+    recs = [run_step(llp, dg, src, ws, dist, lev, kw, True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    return t, recs
 
 
 def main():
@@ -59,6 +120,15 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    wpath = llp.default_sched_weights_path()
+    have_w = os.path.exists(wpath)
+    if have_w:
+        llp.set_sched_weights(np.load(wpath))
+    head = a.sched if a.sched != "auto" else ("learned" if have_w else "plain")
+    if head == "learned" and not have_w:
+        print(json.dumps({"error": f"{wpath} is missing: train the scheduler first"}))
+        sys.exit(1)
+
     t0 = time.time()
     g = llpgen.rmat_graph(a.scale, seed=22)
     src = llpgen.max_outdeg_source(g)
@@ -67,58 +137,37 @@ def main():
     n, m = g.n, g.m
     print(f"# graph scale {a.scale}: n={n} m={m} source={src} built in {time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
-
-    sched = {"plain": dict(sched=llp.SCHED_PLAIN), "hybrid": dict(sched=llp.SCHED_HYBRID),
-             "dense": dict(sched=llp.SCHED_FIXED, flags=llp.DENSE),
-             "push": dict(sched=llp.SCHED_FIXED, flags=llp.PUSH),
-             "learned": dict(sched=llp.SCHED_LEARNED)}[a.sched]
-    if a.delta > 0:
-        if sched["sched"] == llp.SCHED_PLAIN:
-            sched = dict(sched=llp.SCHED_FIXED)
-        sched["delta"] = a.delta
-    if a.sched == "learned":
-        wpath = os.path.join(ROOT, "paper_2603_13147_amd", "sched_weights.npy")
-        llp.set_sched_weights(np.load(wpath))
     ws = llp.workspace(llp.KIND_SSSP, n, m)
     dist = torch.empty(n, dtype=torch.int32, device="cuda")
     lev = torch.empty(n, dtype=torch.int32, device="cuda")
 
-    def step(timing):
-        s1, s2 = llp.Stats(), llp.Stats()
-        fl = sched.get("flags", 0) | (llp.TIMING if timing else 0)
-        kw = dict(sched)
-        kw["flags"] = fl
-        llp.sssp(dg, src, out=dist, ws=ws, stats=s1, **kw)
-        llp.bfs(dg, src, out=lev, ws=ws, stats=s2, **kw)
-        return s1, s2
-
+    kw = sched_kw(llp, head, a.delta)
     steps = a.profile_steps or a.steps
     warm = 0 if a.profile_steps else a.warmup
-    for _ in range(warm):
-        step(False)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    recs = [step(True) for _ in range(steps)]
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    step_s = (t2 - t1) / steps
+    step_s, recs = time_steps(llp, dg, src, ws, dist, lev, kw, steps, warm, torch)
     value = 2 * m / step_s / 1e9
+    print(f"# headline {head}: {step_s * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
 
-    # per-solve rates and the evaluation kernel's roofline (algorithmic bytes:
-    # 12 B per SSSP in-arc read (source id, weight, gathered state), 8 B per BFS
-    # in-arc (no weight), 16 B per candidate (worklist entry)).
-    sssp_ms = np.mean([s1.device_ms for s1, _ in recs])
-    bfs_ms = np.mean([s2.device_ms for _, s2 in recs])
-    kb = 0.0
-    kt = 0.0
-    launches = 0
+    # dominant kernel of the headline step and its roofline
+    mb = pb = mt = pt = 0.0
+    ml = pl = 0
     for s1, s2 in recs:
-        kb += 12.0 * s1.edges_inspected + 16.0 * s1.candidates
-        kb += 8.0 * s2.edges_inspected + 16.0 * s2.candidates
-        kt += s1.kernel_ms + s2.kernel_ms
-        launches += s1.eval_launches + s2.eval_launches
+        for s, weighted in ((s1, True), (s2, False)):
+            x, y = kernel_bytes(s, weighted)
+            mb += x
+            pb += y
+            mt += s.kernel_ms
+            pt += s.pre_ms
+            ml += s.eval_launches
+            pl += s.pre_launches
+    if pt > mt:
+        kname, kb, kt, kl = "k_graph_pre (successor expansion / push)", pb, pt, pl
+    else:
+        kname, kb, kt, kl = "k_graph_main (pull evaluation)", mb, mt, ml
     achieved = kb / (kt * 1e-3) / 1e9 if kt > 0 else 0.0
     s1, s2 = recs[-1]
+    sssp_ms = float(np.mean([r[0].device_ms for r in recs]))
+    bfs_ms = float(np.mean([r[1].device_ms for r in recs]))
     out = {
         "metric": "SSSP/BFS GTEPS to LLP fixpoint",
         "value": round(value, 4),
@@ -133,21 +182,78 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": f"rmat-scale{a.scale} sssp+bfs (a,b,c,d)=(.57,.19,.19,.05), relabelled, "
-                               f"+hamiltonian cycle, w U[1,255] / unit, source max-outdeg",
-                   "n": n, "m": m, "schedule": a.sched + (f"+delta{a.delta}" if a.delta else "")},
-        "sssp": {"gteps": round(m / (sssp_ms * 1e-3) / 1e9, 4), "ms": round(float(sssp_ms), 3),
-                 "rounds": s1.rounds, "edges_inspected": s1.edges_inspected,
+                               f"+hamiltonian cycle, w U[1,255] / unit, source max-outdeg, seed 22",
+                   "n": n, "m": m, "schedule": head + (f"+delta{a.delta}" if a.delta else "")},
+        "sssp": {"gteps": round(m / (sssp_ms * 1e-3) / 1e9, 4), "ms": round(sssp_ms, 3),
+                 "rounds": s1.rounds, "edges_inspected": s1.edges_inspected, "push_edges": s1.push_edges,
                  "expand_edges": s1.expand_edges, "candidates": s1.candidates},
-        "bfs": {"gteps": round(m / (bfs_ms * 1e-3) / 1e9, 4), "ms": round(float(bfs_ms), 3),
-                "rounds": s2.rounds, "edges_inspected": s2.edges_inspected,
+        "bfs": {"gteps": round(m / (bfs_ms * 1e-3) / 1e9, 4), "ms": round(bfs_ms, 3),
+                "rounds": s2.rounds, "edges_inspected": s2.edges_inspected, "push_edges": s2.push_edges,
                 "expand_edges": s2.expand_edges, "candidates": s2.candidates},
-        "roofline": {"kernel": "k_graph_main (pull evaluation)", "bound": "hbm",
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "launches": launches, "avg_launch_us": round(kt * 1e3 / max(launches, 1), 2),
-                     "bytes_per_launch": round(kb / max(launches, 1), 1)},
+        "roofline": {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "launches": kl, "avg_launch_us": round(kt * 1e3 / max(kl, 1), 2),
+                     "bytes_per_launch": round(kb / max(kl, 1), 1),
+                     "other_kernel_ms_per_step": round((mt if pt > mt else pt) / steps, 3)},
     }
-    if not a.no_cpu_baseline and not a.profile_steps:
+    if a.profile_steps:
+        print(json.dumps(out), flush=True)
+        return
+
+    if not a.no_compare:
+        cmp = {}
+        for name in ["plain", "hybrid", "push", "dense"] + (["learned"] if have_w else []):
+            t, rr = time_steps(llp, dg, src, ws, dist, lev, sched_kw(llp, name), 3, 1, torch)
+            cmp[name] = {"ms_per_step": round(t * 1e3, 3),
+                         "sssp_ms": round(float(np.mean([r[0].device_ms for r in rr])), 3),
+                         "bfs_ms": round(float(np.mean([r[1].device_ms for r in rr])), 3)}
+            print(f"# {name}: {t * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+        entry = {"schedules": cmp}
+        if have_w:
+            entry["speedup_learned_vs_plain"] = round(cmp["plain"]["ms_per_step"] / cmp["learned"]["ms_per_step"], 3)
+        out["learned_vs_plain"] = entry
+
+    if a.heldout and have_w:
+        held = {}
+        for name, gg in (("rmat22-s900", llpgen.rmat_graph(22, seed=900)),
+                         ("grid4096-s900", llpgen.grid_graph(4096, 4096, seed=900))):
+            s = llpgen.max_outdeg_source(gg)
+            dgh = llp.DeviceGraph(llpgen.CSRGraph(gg, weighted=True, out_weights=True))
+            wsh = llp.workspace(llp.KIND_SSSP, gg.n, gg.m)
+            o1 = torch.empty(gg.n, dtype=torch.int32, device="cuda")
+            o2 = torch.empty(gg.n, dtype=torch.int32, device="cuda")
+            res = {}
+            for nm, o in (("plain", o1), ("learned", o2)):
+                st = llp.Stats()
+                llp.sssp(dgh, s, out=o, ws=wsh, **sched_kw(llp, nm))           # warm
+                llp.sssp(dgh, s, out=o, ws=wsh, stats=st, flags=llp.TIMING, **sched_kw(llp, nm))
+                res[nm] = round(st.device_ms, 3)
+            torch.cuda.synchronize()
+            held[name] = {"sssp_plain_ms": res["plain"], "sssp_learned_ms": res["learned"],
+                          "speedup": round(res["plain"] / res["learned"], 3),
+                          "bit_exact": bool(torch.equal(o1, o2))}
+            print(f"# held-out {name}: {held[name]}", file=sys.stderr, flush=True)
+            del dgh, wsh, o1, o2
+        out.setdefault("learned_vs_plain", {})["heldout_sssp"] = held
+
+    if not a.no_batch:
+        items = llpgen.batch_workload(4096, 4096, seed=5)
+        b = llp.Batch(items)
+        b.solve(graph=True)                      # measure, capture, instantiate
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(5):
+            st = llp.Stats()
+            b.solve(graph=True, stats=st, flags=llp.TIMING)
+            ts.append(st.device_ms)
+        med = float(np.median(ts))
+        out["batch"] = {"workload": "4096 knapsack (items U[16,256], W U[256,4096]) + 4096 sssp "
+                                    "(n U[256,4096], 8n arcs + cycle, w U[1,100]), seed 5, hipGraph replay",
+                        "instances": b.count, "ms": round(med, 3),
+                        "solves_per_s": round(b.count / (med * 1e-3), 1)}
+        print(f"# batch: {med:.3f} ms", file=sys.stderr, flush=True)
+
+    if not a.no_cpu_baseline:
         import oracle
         t3 = time.perf_counter()
         oracle.sssp(n, g.src, g.dst, g.w, src, bag=True)

@@ -22,6 +22,7 @@
 // few rounds.
 #include <string.h>
 
+#include <map>
 #include <vector>
 
 #include "llp_host.h"
@@ -543,7 +544,7 @@ struct GraphLayout {
 static GraphLayout graph_layout(int64_t m) {
     const DeviceInfo& d = device_info();
     GraphLayout L;
-    L.nseg = d.cus * 4;
+    L.nseg = d.cus * 2;   // one workgroup per segment; all resident at once
     if (L.nseg > MAX_SEG) L.nseg = MAX_SEG;
     long long W = (long long)L.nseg * GW;
     long long per_wave = (m + W - 1) / W;
@@ -580,6 +581,21 @@ static size_t graph_ws(int64_t n, int64_t m, GArgs* a, char* base, size_t cap) {
 }
 
 size_t graph_workspace_bytes(int64_t n, int64_t m) { return graph_ws(n, m, nullptr, nullptr, 0); }
+
+// LLP_TIMING events, created once per thread and device and reused by every
+// solve (creating events per launch would cost more than short rounds).
+static hipEvent_t timing_event(size_t i) {
+    static thread_local std::map<int, std::vector<hipEvent_t>> pool;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::vector<hipEvent_t>& v = pool[dev];
+    while (v.size() <= i) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        v.push_back(e);
+    }
+    return v[i];
+}
 
 static int launch_grid_1d(int64_t work) {
     int64_t g = (work + 255) / 256;
@@ -638,8 +654,9 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     const bool timing = (o.flags & LLP_TIMING) && o.stats;
     if (timing) {
-        LLP_HIP(hipEventCreate(&ev0));
-        LLP_HIP(hipEventCreate(&ev1));
+        ev0 = timing_event(0);
+        ev1 = timing_event(1);
+        if (!ev0 || !ev1) return fail(LLP_E_HIP, "hipEventCreate failed");
         LLP_HIP(hipEventRecord(ev0, st));
     }
     const int g1 = launch_grid_1d(g->n > g->m ? g->n : g->m);
@@ -662,9 +679,9 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
     for (;;) {
         for (int i = 0; i < batch && r <= max_rounds; ++i, ++r) {
             if (timing) {
-                hipEvent_t p0, p1;
-                LLP_HIP(hipEventCreate(&p0));
-                LLP_HIP(hipEventCreate(&p1));
+                hipEvent_t p0 = timing_event(2 + evs.size() + pevs.size());
+                hipEvent_t p1 = timing_event(3 + evs.size() + pevs.size());
+                if (!p0 || !p1) return fail(LLP_E_HIP, "hipEventCreate failed");
                 LLP_HIP(hipEventRecord(p0, st));
                 hipLaunchKernelGGL(k_graph_pre, dim3(a.nseg), dim3(GB), 0, st, a, (int)r);
                 LLP_HIP(hipEventRecord(p1, st));
@@ -674,9 +691,9 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
                 hipLaunchKernelGGL(k_graph_pre, dim3(a.nseg), dim3(GB), 0, st, a, (int)r);
             }
             if (timing) {
-                hipEvent_t e0, e1;
-                LLP_HIP(hipEventCreate(&e0));
-                LLP_HIP(hipEventCreate(&e1));
+                hipEvent_t e0 = timing_event(2 + evs.size() + pevs.size());
+                hipEvent_t e1 = timing_event(3 + evs.size() + pevs.size());
+                if (!e0 || !e1) return fail(LLP_E_HIP, "hipEventCreate failed");
                 LLP_HIP(hipEventRecord(e0, st));
                 hipLaunchKernelGGL(k_graph_main, dim3(a.nseg), dim3(GB), 0, st, a, (int)r, 0);
                 LLP_HIP(hipEventRecord(e1, st));
@@ -733,12 +750,7 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
             o.stats->pre_ms = pms;
         }
     }
-    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
-    for (hipEvent_t e : pevs) (void)hipEventDestroy(e);
-    if (timing) {
-        (void)hipEventDestroy(ev0);
-        (void)hipEventDestroy(ev1);
-    }
+
     if (h.diag[0]) {
         return fail(LLP_E_INPUT, "index guard %d fired: index %d bound %d context %d %d (round %lld)", h.diag[0],
                     h.diag[1], h.diag[2], h.diag[3], h.diag[4], h.rounds);

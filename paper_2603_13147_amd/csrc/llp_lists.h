@@ -43,15 +43,22 @@ struct SegView {
 __device__ inline void load_segments(const unsigned long long* seg, int nseg, int* lds_cnt, int* lds_epre,
                                      int* lds_tmp /* >= blockDim/64 + 1 ints */, int* tot_edges, int* tot_count) {
     const int t = threadIdx.x, nt = blockDim.x;
-    const int per = (nseg + nt - 1) / nt;
+    const int per = (nseg + nt - 1) / nt;   // <= 8 (nseg <= 2048, >= 256 threads)
     const int b = t * per, e = min(b + per, nseg);
     int se = 0, sc = 0;
-    for (int i = b; i < e; ++i) {
-        unsigned long long x = seg[i];
-        int c = (int)(x & 0xffffffffull), ed = (int)(x >> 32);
-        lds_cnt[i] = c;
-        sc += c;
-        se += ed;
+    int eds[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int i = b + k;
+        eds[k] = 0;
+        if (k < per && i < e) {
+            unsigned long long x = seg[i];
+            int c = (int)(x & 0xffffffffull), ed = (int)(x >> 32);
+            lds_cnt[i] = c;
+            eds[k] = ed;
+            sc += c;
+            se += ed;
+        }
     }
     // block exclusive scan of se (edges) and total of sc (counts)
     int w = t >> 6, l = lane();
@@ -72,10 +79,13 @@ __device__ inline void load_segments(const unsigned long long* seg, int nseg, in
         ctot += wcnt[k];
     }
     int run = woff + incl - se;
-    for (int i = b; i < e; ++i) {
-        lds_epre[i] = run;
-        unsigned long long x = seg[i];
-        run += (int)(x >> 32);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int i = b + k;
+        if (k < per && i < e) {
+            lds_epre[i] = run;
+            run += eds[k];
+        }
     }
     if (t == 0) lds_epre[nseg] = etot;
     *tot_edges = etot;

@@ -31,10 +31,13 @@ import llpgen  # noqa: E402
 import paper_2603_13147_amd as llp  # noqa: E402
 
 PLAIN = llp.round_code(llp.MODE_PULL, llp.DCLASS_NONE)
-ACTIONS = [llp.round_code(m, d) for m in (llp.MODE_PULL, llp.MODE_DENSE, llp.MODE_PUSH)
-           for d in (llp.DCLASS_BASE, llp.DCLASS_WIDE, llp.DCLASS_NONE)
-           if not (m == llp.MODE_DENSE and d != llp.DCLASS_NONE)]
-
+PUSH = llp.round_code(llp.MODE_PUSH, llp.DCLASS_NONE)
+# candidate round codes, in order of preference when their costs tie (within
+# TIE of the best): no buckets before buckets, push before pull before dense
+ACTIONS = [PUSH, PLAIN, llp.round_code(llp.MODE_DENSE, llp.DCLASS_NONE),
+           llp.round_code(llp.MODE_PUSH, llp.DCLASS_WIDE), llp.round_code(llp.MODE_PUSH, llp.DCLASS_BASE),
+           llp.round_code(llp.MODE_PULL, llp.DCLASS_WIDE), llp.round_code(llp.MODE_PULL, llp.DCLASS_BASE)]
+TIE = 0.005
 
 def init_params(seed=0):
     """He-uniform weights, zero biases (float32[LLP_MLP_PARAMS])."""
@@ -55,6 +58,7 @@ def solve_fn(kind):
 
 
 def timed(fn, dg, source, ws, out, reps, **kw):
+    """Smallest device time (ms) of `reps` solves."""
     import torch
     ts = []
     flags = kw.pop("flags", 0) | llp.TIMING
@@ -63,11 +67,23 @@ def timed(fn, dg, source, ws, out, reps, **kw):
         fn(dg, source, out=out, ws=ws, stats=st, flags=flags, **kw)
         ts.append(st.device_ms)
     torch.cuda.synchronize()
-    return float(np.median(ts))
+    return float(np.min(ts))
 
 
-def label_graph(name, g, kinds, max_rows, horizon, reps, log):
-    """Features and labels of sampled rounds of the plain sweep on g."""
+def behaviours(seed):
+    """Schedules whose rounds are labelled: their histories are what the
+    network sees as features when it runs (plain, push and a random mix)."""
+    return [("plain", dict(sched=llp.SCHED_PLAIN)), ("push", dict(sched=llp.SCHED_FIXED, flags=llp.PUSH)),
+            ("random", dict(sched=llp.SCHED_RANDOM, seed=seed))]
+
+
+def label_graph(name, g, kinds, max_rows, horizon, reps, log, seed=0):
+    """Features and labels of sampled rounds of several schedules on g.
+
+    Round r of a behaviour schedule is labelled with the round code a whose
+    rollout -- the behaviour's own codes for rounds < r, a for rounds
+    r .. r+h-1, push afterwards -- reaches the fixpoint in the least device
+    time."""
     import torch
     s = llpgen.max_outdeg_source(g)
     csr = llpgen.CSRGraph(g, weighted=True, out_weights=True)
@@ -77,27 +93,32 @@ def label_graph(name, g, kinds, max_rows, horizon, reps, log):
     X, Y = [], []
     for kind in kinds:
         fn = solve_fn(kind)
-        cap = 4 * g.n + 64
-        trace = llp.trace_buffer(min(cap, 1 << 20))
-        st = llp.Stats()
-        fn(dg, s, out=out, ws=ws, stats=st, flags=llp.TRACE, trace=trace)
-        R = int(st.rounds)
-        F = llp.trace_features(trace, R, g.n, g.m).cpu().numpy()
-        rows = np.arange(1, R + 1) if R <= max_rows else np.unique(np.linspace(1, R, max_rows).astype(int))
-        base = timed(fn, dg, s, ws, out, reps)
-        t0 = time.time()
-        counts = {}
-        for r in rows:
-            costs = []
-            for a in ACTIONS:
-                plan = torch.tensor([PLAIN] * (int(r) - 1) + [a] * horizon, dtype=torch.int32, device="cuda")
-                costs.append(timed(fn, dg, s, ws, out, reps, sched=llp.SCHED_SCRIPT, plan=plan))
-            best = ACTIONS[int(np.argmin(costs))]
-            X.append(F[r - 1])
-            Y.append(best)
-            counts[best] = counts.get(best, 0) + 1
-        log(f"{name} {kind}: n={g.n} m={g.m} rounds={R} plain={base:.3f} ms labelled={len(rows)} "
-            f"in {time.time() - t0:.1f}s labels={counts}")
+        for bname, bkw in behaviours(seed):
+            cap = min(4 * g.n + 64, 1 << 20)
+            trace = llp.trace_buffer(cap)
+            st = llp.Stats()
+            fn(dg, s, out=out, ws=ws, stats=st, flags=llp.TRACE, trace=trace, **bkw)
+            R = int(st.rounds)
+            rec = llp.trace_records(trace, R)
+            codes = [int(c) for c in rec["mode"]]
+            F = llp.trace_features(trace, R, g.n, g.m).cpu().numpy()
+            rows = np.arange(1, R + 1) if R <= max_rows else np.unique(np.linspace(1, R, max_rows).astype(int))
+            tail = [PUSH] * (R + 64)
+            t0 = time.time()
+            counts = {}
+            for r in rows:
+                costs = []
+                for a in ACTIONS:
+                    plan = torch.tensor(codes[:int(r) - 1] + [a] * horizon + tail, dtype=torch.int32,
+                                        device="cuda")
+                    costs.append(timed(fn, dg, s, ws, out, reps, sched=llp.SCHED_SCRIPT, plan=plan))
+                best = min(costs)
+                lab = next(a for a, c in zip(ACTIONS, costs) if c <= best * (1 + TIE))
+                X.append(F[r - 1])
+                Y.append(lab)
+                counts[lab] = counts.get(lab, 0) + 1
+            log(f"{name} {kind} under {bname}: n={g.n} m={g.m} rounds={R} labelled={len(rows)} "
+                f"in {time.time() - t0:.1f}s labels={counts}")
     return X, Y
 
 
@@ -140,8 +161,8 @@ def training_graphs(quick=False):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
-    ap.add_argument("--rows", type=int, default=40, help="rounds labelled per trace")
-    ap.add_argument("--grid-rows", type=int, default=24)
+    ap.add_argument("--rows", type=int, default=16, help="rounds labelled per trace")
+    ap.add_argument("--grid-rows", type=int, default=12)
     ap.add_argument("--horizon", type=int, default=4)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--steps", type=int, default=3000)
@@ -157,7 +178,7 @@ def main(argv=None):
     for name, g, kinds in training_graphs(a.quick):
         rows = a.grid_rows if name.startswith("grid") else a.rows
         reps = 2 if name.startswith("grid") else a.reps
-        x, y = label_graph(name, g, kinds, rows, a.horizon, reps, log)
+        x, y = label_graph(name, g, kinds, rows, a.horizon, reps, log, seed=a.seed)
         X += x
         Y += y
     p, acc = fit(X, Y, a.steps, a.lr, a.seed, log)
