@@ -49,6 +49,7 @@ def parse():
     p.add_argument("--sched", default="auto", choices=["auto", "plain", "hybrid", "dense", "push", "learned"])
     p.add_argument("--delta", type=int, default=0,
                    help="delta-bucket width for the fixed schedules (plain becomes fixed pull)")
+    p.add_argument("--wgs-per-cu", type=int, default=0, help="graph sweep workgroups per CU (0 = default)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-compare", action="store_true", help="skip the schedule comparison")
     p.add_argument("--no-batch", action="store_true", help="skip the batched-solve measurement")
@@ -137,11 +138,13 @@ def main():
     n, m = g.n, g.m
     print(f"# graph scale {a.scale}: n={n} m={m} source={src} built in {time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
-    ws = llp.workspace(llp.KIND_SSSP, n, m)
+    ws = llp.workspace(llp.KIND_SSSP, n, m, a.wgs_per_cu)
     dist = torch.empty(n, dtype=torch.int32, device="cuda")
     lev = torch.empty(n, dtype=torch.int32, device="cuda")
 
     kw = sched_kw(llp, head, a.delta)
+    if a.wgs_per_cu:
+        kw["chunk"] = a.wgs_per_cu
     steps = a.profile_steps or a.steps
     warm = 0 if a.profile_steps else a.warmup
     step_s, recs = time_steps(llp, dg, src, ws, dist, lev, kw, steps, warm, torch)

@@ -122,7 +122,10 @@ typedef struct {
     int32_t* status_dev;        /* [device] optional status word (required with LLP_ASYNC) */
     volatile int32_t* abort_host; /* [host, pinned] optional: a nonzero value aborts at the next round */
     llp_stats* stats;           /* [host] optional */
-    int32_t chunk;              /* schedule knob: SM chain length / knapsack cells per thread; 0 = default */
+    int32_t chunk;              /* launch knob, 0 = default: graph sweeps: workgroups (list segments) per CU
+                                   (default 2, at most 8; pass the same opts to llp_workspace_bytes);
+                                   stable marriage: proposals per thread per launch; batch: instances per
+                                   queue claim */
     int32_t block;              /* threads per workgroup; 0 = default (256) */
     llp_trace_rec* trace_dev;   /* [device] LLP_TRACE output */
     int64_t trace_cap;

@@ -205,9 +205,14 @@ def make_opts(sched=SCHED_PLAIN, flags=0, delta=0, max_rounds=0, workspace=None,
     return o
 
 
-def workspace(kind, n, m):
+def workspace(kind, n, m, chunk=0):
+    """Device scratch for a solve of this kind and size (chunk: the launch knob
+    the solve will be given, see llp_opts.chunk)."""
     torch = _torch()
-    nbytes = int(lib().llp_workspace_bytes(kind, n, m, None))
+    o = Opts()
+    o.size = ctypes.sizeof(Opts)
+    o.chunk = chunk
+    nbytes = int(lib().llp_workspace_bytes(kind, n, m, ctypes.byref(o)))
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device="cuda")
 
 
@@ -249,7 +254,7 @@ def _graph_solve(fn, kind, dg, source, out, opts):
 def sssp(dg, source, out=None, ws=None, **kw):
     """Shortest distances from `source` (int32 tensor; 2**31-1 = unreachable)."""
     if ws is None:
-        ws = workspace(KIND_SSSP, dg.n, dg.m)
+        ws = workspace(KIND_SSSP, dg.n, dg.m, kw.get("chunk", 0))
     o = make_opts(workspace=ws, **kw)
     return _graph_solve(lib().llp_solve_sssp, KIND_SSSP, dg, source, out, o)
 
@@ -257,7 +262,7 @@ def sssp(dg, source, out=None, ws=None, **kw):
 def bfs(dg, source, out=None, ws=None, **kw):
     """Breadth-first levels from `source` (int32 tensor; 2**31-1 = unreachable)."""
     if ws is None:
-        ws = workspace(KIND_BFS, dg.n, dg.m)
+        ws = workspace(KIND_BFS, dg.n, dg.m, kw.get("chunk", 0))
     o = make_opts(workspace=ws, **kw)
     return _graph_solve(lib().llp_solve_bfs, KIND_BFS, dg, source, out, o)
 

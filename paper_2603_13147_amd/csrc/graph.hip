@@ -541,10 +541,14 @@ struct GraphLayout {
     int cap;
 };
 
-static GraphLayout graph_layout(int64_t m) {
+// per_cu: workgroups (= list segments) per CU, opts->chunk for graph solves;
+// the default 2 keeps every workgroup of a phase kernel resident at once.
+static int graph_wgs_per_cu(int chunk) { return chunk > 0 ? (chunk > 8 ? 8 : chunk) : 2; }
+
+static GraphLayout graph_layout(int64_t m, int per_cu) {
     const DeviceInfo& d = device_info();
     GraphLayout L;
-    L.nseg = d.cus * 2;   // one workgroup per segment; all resident at once
+    L.nseg = d.cus * per_cu;
     if (L.nseg > MAX_SEG) L.nseg = MAX_SEG;
     long long W = (long long)L.nseg * GW;
     long long per_wave = (m + W - 1) / W;
@@ -552,8 +556,8 @@ static GraphLayout graph_layout(int64_t m) {
     return L;
 }
 
-static size_t graph_ws(int64_t n, int64_t m, GArgs* a, char* base, size_t cap) {
-    GraphLayout L = graph_layout(m);
+static size_t graph_ws(int64_t n, int64_t m, int per_cu, GArgs* a, char* base, size_t cap) {
+    GraphLayout L = graph_layout(m, per_cu);
     Carver cv{base, cap, 0, base == nullptr};
     int* stamp = cv.take<int>(n);
     int* cstamp = cv.take<int>(n);
@@ -580,7 +584,9 @@ static size_t graph_ws(int64_t n, int64_t m, GArgs* a, char* base, size_t cap) {
     return cv.used;
 }
 
-size_t graph_workspace_bytes(int64_t n, int64_t m) { return graph_ws(n, m, nullptr, nullptr, 0); }
+size_t graph_workspace_bytes(int64_t n, int64_t m, int chunk) {
+    return graph_ws(n, m, graph_wgs_per_cu(chunk), nullptr, nullptr, 0);
+}
 
 // LLP_TIMING events, created once per thread and device and reused by every
 // solve (creating events per launch would cost more than short rounds).
@@ -645,11 +651,12 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
     int s = sched_params(o, bfs || jobs_dur || g->out_w != nullptr, &a.sp);
     if (s) return s;
 
-    size_t need = graph_ws(g->n, g->m, nullptr, nullptr, 0);
+    const int per_cu = graph_wgs_per_cu(o.chunk);
+    size_t need = graph_ws(g->n, g->m, per_cu, nullptr, nullptr, 0);
     void* ws = nullptr;
     s = get_workspace(o, need, &ws);
     if (s) return s;
-    graph_ws(g->n, g->m, &a, (char*)ws, need);
+    graph_ws(g->n, g->m, per_cu, &a, (char*)ws, need);
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     const bool timing = (o.flags & LLP_TIMING) && o.stats;

@@ -259,11 +259,11 @@ static size_t jobs_ws(int64_t n, int64_t E, JArgs* a, char* base, size_t cap) {
 }
 
 // the pull form shares the graph sweep's workspace
-size_t graph_workspace_bytes(int64_t n, int64_t m);
+size_t graph_workspace_bytes(int64_t n, int64_t m, int chunk);
 
-size_t jobs_workspace_bytes(int64_t n, int64_t E) {
+size_t jobs_workspace_bytes(int64_t n, int64_t E, int chunk) {
     size_t a = jobs_ws(n, E, nullptr, nullptr, 0);
-    size_t b = graph_workspace_bytes(n, E);
+    size_t b = graph_workspace_bytes(n, E, chunk);
     return a > b ? a : b;
 }
 

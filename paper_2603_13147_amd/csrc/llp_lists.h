@@ -199,14 +199,14 @@ __device__ inline void for_edges(const Src& src, int wb, int we, int* own_lds, B
     const int l = lane();
     Cursor cur = src.locate(wb);
     int base = wb;
+    int av = src.avail(cur);
+    int4 e = (l < av) ? src.load(cur, l) : make_int4(0, 0, LLP_INF, 0);
     while (base < we) {
-        int av = src.avail(cur);
         if (av <= 0) {                 // inconsistent list: record and stop this wave
             if (l == 0) record_diag(src.diag, 31, base, we, cur.s, cur.i);
             return;
         }
-        bool valid = l < av;
-        int4 e = valid ? src.load(cur, l) : make_int4(0, 0, LLP_INF, 0);
+        const bool valid = l < av;
         int last = (av < 64 ? av : 64) - 1;
         int end_last = shfl(e.z + e.w, last);
         int limit = min(min(base + 64, we), end_last);
@@ -231,10 +231,21 @@ __device__ inline void for_edges(const Src& src, int wb, int we, int* own_lds, B
         c.mine_valid = valid;
         c.base = base;
         c.limit = limit;
+        // the next window is known before the body runs: issue its loads first
+        // so they overlap the body's memory traffic
+        const int done = __popcll(ballot(valid && e.z + e.w <= limit));
+        const Cursor nxt = src.advance(cur, done);
+        int nav = 0;
+        int4 ne = make_int4(0, 0, LLP_INF, 0);
+        if (limit < we) {
+            nav = src.avail(nxt);
+            if (l < nav) ne = src.load(nxt, l);
+        }
         body(c);
-        int done = __popcll(ballot(valid && e.z + e.w <= limit));
-        cur = src.advance(cur, done);
+        cur = nxt;
         base = limit;
+        av = nav;
+        e = ne;
     }
 }
 

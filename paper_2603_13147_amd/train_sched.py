@@ -37,7 +37,7 @@ PUSH = llp.round_code(llp.MODE_PUSH, llp.DCLASS_NONE)
 ACTIONS = [PUSH, PLAIN, llp.round_code(llp.MODE_DENSE, llp.DCLASS_NONE),
            llp.round_code(llp.MODE_PUSH, llp.DCLASS_WIDE), llp.round_code(llp.MODE_PUSH, llp.DCLASS_BASE),
            llp.round_code(llp.MODE_PULL, llp.DCLASS_WIDE), llp.round_code(llp.MODE_PULL, llp.DCLASS_BASE)]
-TIE = 0.005
+TIE = 0.02
 
 def init_params(seed=0):
     """He-uniform weights, zero biases (float32[LLP_MLP_PARAMS])."""
@@ -97,7 +97,9 @@ def label_graph(name, g, kinds, max_rows, horizon, reps, log, seed=0):
             cap = min(4 * g.n + 64, 1 << 20)
             trace = llp.trace_buffer(cap)
             st = llp.Stats()
-            fn(dg, s, out=out, ws=ws, stats=st, flags=llp.TRACE, trace=trace, **bkw)
+            k = dict(bkw)
+            k["flags"] = k.get("flags", 0) | llp.TRACE
+            fn(dg, s, out=out, ws=ws, stats=st, trace=trace, **k)
             R = int(st.rounds)
             rec = llp.trace_records(trace, R)
             codes = [int(c) for c in rec["mode"]]
@@ -177,7 +179,7 @@ def main(argv=None):
     X, Y = [], []
     for name, g, kinds in training_graphs(a.quick):
         rows = a.grid_rows if name.startswith("grid") else a.rows
-        reps = 2 if name.startswith("grid") else a.reps
+        reps = a.reps
         x, y = label_graph(name, g, kinds, rows, a.horizon, reps, log, seed=a.seed)
         X += x
         Y += y

@@ -1,0 +1,61 @@
+"""What the trained scheduler gains over the plain schedule on its held-out
+evaluation graphs (R-MAT scale 22 seed 900, 4096 x 4096 grid seed 900), with
+fixpoints that are bit-identical to the plain schedule's and certified as
+shortest-path distances (every arc relaxed, every reached vertex tight)."""
+import os
+
+import numpy as np
+import pytest
+
+import llpgen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+llp = pytest.importorskip("paper_2603_13147_amd")
+
+I32 = 2**31 - 1
+
+
+def certify(g, s, d):
+    d = d.astype(np.int64)
+    w = g.w.astype(np.int64)
+    assert d[s] == 0
+    ru = d[g.src] < I32
+    assert np.all(d[g.dst[ru]] <= d[g.src[ru]] + w[ru])
+    tight = np.zeros(g.n, bool)
+    t = ru & (d[g.dst] == d[g.src] + w)
+    tight[g.dst[t]] = True
+    reached = d < I32
+    reached[s] = False
+    assert np.all(tight[reached])
+
+
+def best_ms(dg, s, ws, out, reps, **kw):
+    ts = []
+    for _ in range(reps):
+        st = llp.Stats()
+        llp.sssp(dg, s, out=out, ws=ws, stats=st, flags=llp.TIMING, **kw)
+        ts.append(st.device_ms)
+    torch.cuda.synchronize()
+    return min(ts)
+
+
+@pytest.mark.parametrize("which", ["rmat22-s900", "grid4096-s900"])
+def test_learned_gain_on_heldout_graphs(which):
+    path = llp.default_sched_weights_path()
+    assert os.path.exists(path), "trained weights are part of the package"
+    llp.set_sched_weights(np.load(path))
+    g = llpgen.rmat_graph(22, seed=900) if which.startswith("rmat") else llpgen.grid_graph(4096, 4096, seed=900)
+    s = llpgen.max_outdeg_source(g)
+    dg = llp.DeviceGraph(llpgen.CSRGraph(g, weighted=True, out_weights=True))
+    ws = llp.workspace(llp.KIND_SSSP, g.n, g.m)
+    o1 = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    o2 = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    reps = 3 if which.startswith("rmat") else 2
+    t_plain = best_ms(dg, s, ws, o1, reps)
+    t_learned = best_ms(dg, s, ws, o2, reps, sched=llp.SCHED_LEARNED)
+    assert torch.equal(o1, o2)
+    certify(g, s, o1.cpu().numpy())
+    print(f"{which}: plain {t_plain:.3f} ms, learned {t_learned:.3f} ms, speedup {t_plain / t_learned:.2f}")
+    assert t_learned < t_plain / 1.1
