@@ -56,6 +56,8 @@ def parse():
     p.add_argument("--heldout", action="store_true", help="also time the learned scheduler's held-out graphs")
     p.add_argument("--profile-steps", type=int, default=0,
                    help="run only this many headline steps, nothing else (for rocprofv3 runs)")
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="only copy a 1 GiB device buffer 3 times (reference for rocprofv3 byte counters)")
     return p.parse_args()
 
 
@@ -121,6 +123,15 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    if a.calibrate_copy:
+        x = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        x.fill_(1)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copied_bytes_per_launch": x.numel() * 4, "launches": 3}), flush=True)
+        return
     wpath = llp.default_sched_weights_path()
     have_w = os.path.exists(wpath)
     if have_w:

@@ -22,6 +22,7 @@
 // few rounds.
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <vector>
 
@@ -45,7 +46,10 @@ struct GCtrl {
     int ovf;
     int verify_changed;
     int dbase;          // delta base width (2^floor(log2 mean weight), from a sample of the arcs)
-    int carried;        // entries carried by the delta filter this round (traced solves)
+    int over;           // the round limit was reached
+    int carried[2];     // entries carried by the delta filter, by round parity (traced solves)
+    int step_phase[2];  // step kernel k: phase[k & 1] 0 = PRE of round step_round + 1, 1 = MAIN of step_round
+    int step_round[2];
     int diag[8];        // first guard event: site, index, bound, context
     long long rounds, cand, edges, adv, xedges, pedges;
     SchedHist hist[2];  // scheduler history, double-buffered by round parity
@@ -72,6 +76,9 @@ struct GArgs {
     GCtrl* ctrl;
     llp_trace_rec* trace;
     long long trace_cap;
+    signed char* plog;     // LLP_TIMING: phase run by step launch k (-1 none, 0 PRE, 1 MAIN)
+    long long plog_cap;
+    long long max_rounds;
     SchedParams sp;
 };
 
@@ -354,15 +361,28 @@ __device__ __forceinline__ int delta_of(const GArgs& a, int code) {
 }
 
 // --------------------------------------------------------------- PRE
-__global__ void __launch_bounds__(GB) k_graph_pre(GArgs a, int r) {
-    __shared__ GShared sh;
-    if (ld_relaxed(&a.ctrl->done) || ld_relaxed(&a.ctrl->status)) return;
+// Round r, first phase: consume CL[r-1], decide the round's code, then
+// expand into WL (pull), push (CL[r]) or nothing (dense).  k: step launch.
+__device__ void pre_phase(const GArgs& a, int r, int k, GShared& sh) {
     const ListRef in = cl_of(a, r - 1);
     const ListRef out = cl_of(a, r);
     load_segments(in.seg, a.nseg, sh.cnt, sh.epre, sh.tmp, &sh.tot_edges, &sh.tot_count);
     const int force_dense = (r == 1 && a.warm_dense);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.trace && r >= 2 && r - 2 < a.trace_cap) {
+        // entries the previous round's delta filter carried
+        a.trace[r - 2].pending = a.ctrl->carried[(r - 1) & 1];
+        a.ctrl->carried[(r - 1) & 1] = 0;
+    }
     if (sh.tot_count == 0 && !force_dense) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
+            a.ctrl->done = 1;
+            a.ctrl->last_round = r - 1;
+        }
+        return;
+    }
+    if ((long long)r > a.max_rounds) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            a.ctrl->over = 1;
             a.ctrl->done = 1;
             a.ctrl->last_round = r - 1;
         }
@@ -393,6 +413,10 @@ __global__ void __launch_bounds__(GB) k_graph_pre(GArgs a, int r) {
         GCtrl* c = a.ctrl;
         c->mode = code;
         c->rounds = r;
+        // the next step launch: MAIN of this round, or PRE of the next one after a push
+        c->step_phase[(k + 1) & 1] = mode == MODE_PUSH ? 0 : 1;
+        c->step_round[(k + 1) & 1] = r;
+        if (a.plog && k < a.plog_cap) a.plog[k] = 0;
         c->adv += sh.tot_count;
         if (mode == MODE_PULL) c->xedges += sh.tot_edges;
         if (mode == MODE_PUSH) c->pedges += sh.tot_edges;
@@ -436,20 +460,21 @@ __global__ void __launch_bounds__(GB) k_graph_pre(GArgs a, int r) {
         __syncthreads();
         if (threadIdx.x == 0) publish(out, sh.ctr, sh.cmin);
     }
-    if (threadIdx.x == 0 && sh.carried) atomicAdd(&a.ctrl->carried, sh.carried);
+    if (threadIdx.x == 0 && sh.carried) atomicAdd(&a.ctrl->carried[r & 1], sh.carried);
     if (__any(ovf) && lane() == 0) st_relaxed(&a.ctrl->ovf, 1);
 }
 
 // --------------------------------------------------------------- MAIN
-// verify != 0: a dense round on the final state that must change nothing.
-__global__ void __launch_bounds__(GB) k_graph_main(GArgs a, int r, int verify) {
-    __shared__ GShared sh;
-    if (!verify && (ld_relaxed(&a.ctrl->done) || ld_relaxed(&a.ctrl->status))) return;
+// Round r, second phase (pull and dense rounds): evaluate WL (or every
+// vertex) and produce CL[r].  verify != 0: a dense round on the final state
+// that must change nothing.
+__device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh) {
     const int code = verify ? MODE_DENSE : a.ctrl->mode;
     const int mode = code & 3;
-    if (!verify && blockIdx.x == 0 && threadIdx.x == 0 && a.trace && r - 1 < a.trace_cap) {
-        a.trace[r - 1].pending = a.ctrl->carried;
-        a.ctrl->carried = 0;
+    if (!verify && blockIdx.x == 0 && threadIdx.x == 0) {
+        a.ctrl->step_phase[(k + 1) & 1] = 0;
+        a.ctrl->step_round[(k + 1) & 1] = r;
+        if (a.plog && k < a.plog_cap) a.plog[k] = 1;
     }
     if (mode == MODE_PUSH) return;
     const ListRef out = verify ? a.wl : cl_of(a, r);   // verify writes into WL's storage
@@ -497,6 +522,24 @@ __global__ void __launch_bounds__(GB) k_graph_main(GArgs a, int r, int verify) {
         long long tot = wave_sum64(nadv);
         if (lane() == 0 && tot) st_relaxed(&a.ctrl->verify_changed, 1);
     }
+}
+
+// One step of the sweep: launch k runs the phase the previous launch left in
+// slot k & 1 (PRE of the next round, or MAIN of the current one), so a push
+// round costs one launch and a pull or dense round two.  The slots
+// alternate, so no workgroup of launch k reads the slot launch k writes.
+__global__ void __launch_bounds__(GB) k_graph_step(GArgs a, int k) {
+    __shared__ GShared sh;
+    if (ld_relaxed(&a.ctrl->done) || ld_relaxed(&a.ctrl->status)) return;
+    const int ph = a.ctrl->step_phase[k & 1];
+    const int rr = a.ctrl->step_round[k & 1];
+    if (ph == 0) pre_phase(a, rr + 1, k, sh);
+    else main_phase(a, rr, 0, k, sh);
+}
+
+__global__ void __launch_bounds__(GB) k_graph_verify(GArgs a, int r) {
+    __shared__ GShared sh;
+    main_phase(a, r, 1, 0, sh);
 }
 
 // --------------------------------------------------------------- finish
@@ -562,6 +605,8 @@ static size_t graph_ws(int64_t n, int64_t m, int per_cu, GArgs* a, char* base, s
     int* stamp = cv.take<int>(n);
     int* cstamp = cv.take<int>(n);
     GCtrl* ctrl = cv.take<GCtrl>(1);
+    const long long plog_cap = 8 * n + 512;   // covers the default round limit's launches
+    signed char* plog = cv.take<signed char>(plog_cap);
     ListRef lists[3];
     for (int i = 0; i < 3; ++i) {
         // CL lists hold the entries a delta round carries plus the round's own
@@ -580,12 +625,19 @@ static size_t graph_ws(int64_t n, int64_t m, int per_cu, GArgs* a, char* base, s
         a->cl0 = lists[1];
         a->cl1 = lists[2];
         a->nseg = L.nseg;
+        a->plog = plog;
+        a->plog_cap = plog_cap;
     }
     return cv.used;
 }
 
 size_t graph_workspace_bytes(int64_t n, int64_t m, int chunk) {
     return graph_ws(n, m, graph_wgs_per_cu(chunk), nullptr, nullptr, 0);
+}
+
+__global__ void k_fill_i8(signed char* p, long long n, signed char v) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
 // LLP_TIMING events, created once per thread and device and reused by every
@@ -676,51 +728,48 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
     // graph limit
     const int64_t max_rounds =
         o.max_rounds > 0 ? o.max_rounds : (jobs_dur ? (int64_t)g->n + 2 : 4 * (int64_t)g->n + 64);
+    a.max_rounds = max_rounds;
     GCtrl h;
     memset(&h, 0, sizeof(h));
-    int64_t r = 1;
-    int batch = 4;
+    // step launches: at most two per round; the batch doubles up to 32
+    const int64_t max_launches = 2 * max_rounds + 4;
+    int64_t k = 0;
+    int batch = 8;
     int status = LLP_OK;
-    std::vector<hipEvent_t> evs;     // LLP_TIMING: one pair around each MAIN launch
-    std::vector<hipEvent_t> pevs;    // and around each PRE launch
+    std::vector<hipEvent_t> evs;     // LLP_TIMING: one pair around each step launch
+    if (timing && a.plog) {
+        hipLaunchKernelGGL(k_fill_i8, dim3(launch_grid_1d(a.plog_cap)), dim3(256), 0, st, a.plog, a.plog_cap,
+                           (signed char)-1);
+    }
     for (;;) {
-        for (int i = 0; i < batch && r <= max_rounds; ++i, ++r) {
+        for (int i = 0; i < batch && k < max_launches; ++i, ++k) {
             if (timing) {
-                hipEvent_t p0 = timing_event(2 + evs.size() + pevs.size());
-                hipEvent_t p1 = timing_event(3 + evs.size() + pevs.size());
-                if (!p0 || !p1) return fail(LLP_E_HIP, "hipEventCreate failed");
-                LLP_HIP(hipEventRecord(p0, st));
-                hipLaunchKernelGGL(k_graph_pre, dim3(a.nseg), dim3(GB), 0, st, a, (int)r);
-                LLP_HIP(hipEventRecord(p1, st));
-                pevs.push_back(p0);
-                pevs.push_back(p1);
-            } else {
-                hipLaunchKernelGGL(k_graph_pre, dim3(a.nseg), dim3(GB), 0, st, a, (int)r);
-            }
-            if (timing) {
-                hipEvent_t e0 = timing_event(2 + evs.size() + pevs.size());
-                hipEvent_t e1 = timing_event(3 + evs.size() + pevs.size());
+                hipEvent_t e0 = timing_event(2 + evs.size());
+                hipEvent_t e1 = timing_event(3 + evs.size());
                 if (!e0 || !e1) return fail(LLP_E_HIP, "hipEventCreate failed");
                 LLP_HIP(hipEventRecord(e0, st));
-                hipLaunchKernelGGL(k_graph_main, dim3(a.nseg), dim3(GB), 0, st, a, (int)r, 0);
+                hipLaunchKernelGGL(k_graph_step, dim3(a.nseg), dim3(GB), 0, st, a, (int)k);
                 LLP_HIP(hipEventRecord(e1, st));
                 evs.push_back(e0);
                 evs.push_back(e1);
             } else {
-                hipLaunchKernelGGL(k_graph_main, dim3(a.nseg), dim3(GB), 0, st, a, (int)r, 0);
+                hipLaunchKernelGGL(k_graph_step, dim3(a.nseg), dim3(GB), 0, st, a, (int)k);
             }
         }
         LLP_HIP(hipGetLastError());
         s = readback(st, a.ctrl, &h, sizeof(h));
         if (s) return s;
         if (h.status) break;
-        if (h.done) break;
+        if (h.done) {
+            if (h.over) status = LLP_E_NOT_CONVERGED;
+            break;
+        }
         if (o.abort_host && *o.abort_host) { status = LLP_E_ABORTED; break; }
-        if (r > max_rounds) { status = LLP_E_NOT_CONVERGED; break; }
-        if (batch < 16) batch *= 2;
+        if (k >= max_launches) { status = LLP_E_NOT_CONVERGED; break; }
+        if (batch < 32) batch *= 2;
     }
     if (status == LLP_OK && h.status == 0 && (o.flags & LLP_VERIFY)) {
-        hipLaunchKernelGGL(k_graph_main, dim3(a.nseg), dim3(GB), 0, st, a, (int)h.last_round + 1, 1);
+        hipLaunchKernelGGL(k_graph_verify, dim3(a.nseg), dim3(GB), 0, st, a, (int)h.last_round + 1);
     }
     if (h.status == 0) hipLaunchKernelGGL(k_graph_ovf, dim3(g1), dim3(256), 0, st, a);
     if (!jobs_dur) hipLaunchKernelGGL(k_graph_decode, dim3(launch_grid_1d(g->n)), dim3(256), 0, st, out, g->n);
@@ -735,29 +784,32 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
         o.stats->edges_inspected = h.edges;
         o.stats->advances = h.adv;
         o.stats->expand_edges = h.xedges;
-        o.stats->eval_launches = (int64_t)(evs.size() / 2);
-        o.stats->pre_launches = (int64_t)(pevs.size() / 2);
         o.stats->push_edges = h.pedges;
         if (timing) {
-            float ms = 0.f, kms = 0.f;
-            LLP_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-            for (size_t i = 0; i + 1 < evs.size(); i += 2) {
-                float t = 0.f;
-                LLP_HIP(hipEventElapsedTime(&t, evs[i], evs[i + 1]));
-                kms += t;
+            const size_t nl = evs.size() / 2;
+            std::vector<signed char> ph(nl, -1);
+            if (a.plog && nl) {
+                s = readback(st, a.plog, ph.data(), std::min<size_t>(nl, (size_t)a.plog_cap));
+                if (s) return s;
             }
-            float pms = 0.f;
-            for (size_t i = 0; i + 1 < pevs.size(); i += 2) {
+            float ms = 0.f, kms = 0.f, pms = 0.f;
+            LLP_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+            for (size_t i = 0; i < nl; ++i) {
                 float t = 0.f;
-                LLP_HIP(hipEventElapsedTime(&t, pevs[i], pevs[i + 1]));
-                pms += t;
+                LLP_HIP(hipEventElapsedTime(&t, evs[2 * i], evs[2 * i + 1]));
+                if (ph[i] == 1) {
+                    kms += t;
+                    o.stats->eval_launches++;
+                } else if (ph[i] == 0) {
+                    pms += t;
+                    o.stats->pre_launches++;
+                }
             }
             o.stats->device_ms = ms;
             o.stats->kernel_ms = kms;
             o.stats->pre_ms = pms;
         }
     }
-
     if (h.diag[0]) {
         return fail(LLP_E_INPUT, "index guard %d fired: index %d bound %d context %d %d (round %lld)", h.diag[0],
                     h.diag[1], h.diag[2], h.diag[3], h.diag[4], h.rounds);
