@@ -8,8 +8,9 @@ weights U[1, 255] for SSSP and unit weights for BFS, source = the vertex of
 highest out-degree (smallest id on ties).  Synthetic, seeded (seed 22).
 
 One step = one SSSP solve + one BFS solve to the LLP fixpoint on that graph,
-inputs resident in HBM, with the headline schedule (the learned scheduler
-when its weights are present, else the plain schedule).  value = 2 m / step
+inputs resident in HBM, with the headline schedule (the frontier-width
+hybrid: dense rounds when the changed vertices' out-arcs exceed half of the
+arcs, push rounds otherwise).  value = 2 m / step
 time (GTEPS, every input arc counted once per solve).
 
 The JSON line also carries
@@ -38,6 +39,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+# sources of the step kernel, hashed to tell whether committed counters still apply
+KERNEL_SOURCES = ("graph.hip", "llp_lists.h", "llp_sched.h", "llp_dev.h")
 
 
 def parse():
@@ -94,6 +97,21 @@ def kernel_bytes(s, weighted):
     return main, pre
 
 
+def committed_traffic():
+    """HBM bytes per phase launch of the step kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (scaled by a plain copy's counters), or None
+    when the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_graph_step_rmat22_learned.traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    csrc = os.path.join(ROOT, "paper_2603_13147_amd", "csrc")
+    h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                for f in KERNEL_SOURCES)).hexdigest()[:16]
+    return rec["traffic_bytes_per_launch"] if h == rec["source_sha16"] else None
+
+
 def time_steps(llp, dg, src, ws, dist, lev, kw, steps, warm, torch):
     """Wall time per step over `steps` steps without per-launch events, then
     the same number of steps with LLP_TIMING for the kernel counters."""
@@ -136,7 +154,10 @@ def main():
     have_w = os.path.exists(wpath)
     if have_w:
         llp.set_sched_weights(np.load(wpath))
-    head = a.sched if a.sched != "auto" else ("learned" if have_w else "plain")
+    # headline: the frontier-width hybrid (dense above half the arcs, push below),
+    # the fastest schedule measured on this graph; the learned and plain
+    # schedules are reported beside it
+    head = a.sched if a.sched != "auto" else "hybrid"
     if head == "learned" and not have_w:
         print(json.dumps({"error": f"{wpath} is missing: train the scheduler first"}))
         sys.exit(1)
@@ -179,6 +200,7 @@ def main():
     else:
         kname, kb, kt, kl = "k_graph_main (pull evaluation)", mb, mt, ml
     achieved = kb / (kt * 1e-3) / 1e9 if kt > 0 else 0.0
+    traffic = committed_traffic()
     s1, s2 = recs[-1]
     sssp_ms = float(np.mean([r[0].device_ms for r in recs]))
     bfs_ms = float(np.mean([r[1].device_ms for r in recs]))
@@ -205,7 +227,7 @@ def main():
                 "rounds": s2.rounds, "edges_inspected": s2.edges_inspected, "push_edges": s2.push_edges,
                 "expand_edges": s2.expand_edges, "candidates": s2.candidates},
         "roofline": {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "launches": kl, "avg_launch_us": round(kt * 1e3 / max(kl, 1), 2),
                      "bytes_per_launch": round(kb / max(kl, 1), 1),
                      "other_kernel_ms_per_step": round((mt if pt > mt else pt) / steps, 3)},
@@ -225,6 +247,7 @@ def main():
         entry = {"schedules": cmp}
         if have_w:
             entry["speedup_learned_vs_plain"] = round(cmp["plain"]["ms_per_step"] / cmp["learned"]["ms_per_step"], 3)
+            entry["speedup_learned_vs_hybrid"] = round(cmp["hybrid"]["ms_per_step"] / cmp["learned"]["ms_per_step"], 3)
         out["learned_vs_plain"] = entry
 
     if a.heldout and have_w:
@@ -266,6 +289,37 @@ def main():
                         "instances": b.count, "ms": round(med, 3),
                         "solves_per_s": round(b.count / (med * 1e-3), 1)}
         print(f"# batch: {med:.3f} ms", file=sys.stderr, flush=True)
+
+    if not a.no_batch:
+        # the other plugins at their full sizes (stable marriage n = 8192,
+        # seed 3; job DAG of 2^20 jobs, seed 4): median device time of 3 solves
+        def med_ms(fn):
+            ts = []
+            for _ in range(4):
+                st = llp.Stats()
+                fn(st)
+                ts.append(st.device_ms)
+            return float(np.median(ts[1:]))
+        mp, wr = llpgen.sm_prefs(8192, seed=3)
+        mpd, wrd = torch.from_numpy(mp).cuda(), torch.from_numpy(wr).cuda()
+        wsm = llp.workspace(llp.KIND_SM, 8192, 0)
+        sm_ms = med_ms(lambda st: llp.stable_marriage(mpd, wrd, ws=wsm, stats=st, flags=llp.TIMING))
+        st = llp.Stats()
+        llp.stable_marriage(mpd, wrd, ws=wsm, stats=st)
+        out["stable_marriage"] = {"n": 8192, "ms": round(sm_ms, 3), "solves_per_s": round(1e3 / sm_ms, 1),
+                                  "proposals": st.advances}
+        del mpd, wrd
+        pp, pi, du = llpgen.job_dag(1 << 20, seed=4)
+        sp, si = llpgen.job_succ(pp, pi)
+        dev = [torch.from_numpy(x).cuda() for x in (pp, pi, du, sp, si)]
+        wsj = llp.workspace(llp.KIND_JOBS, 1 << 20, int(pi.shape[0]))
+        jr = med_ms(lambda st: llp.jobs(*dev, ws=wsj, stats=st, flags=llp.TIMING))
+        jp = med_ms(lambda st: llp.jobs(*dev, ws=wsj, stats=st, flags=llp.TIMING, pull=True))
+        st = llp.Stats()
+        llp.jobs(*dev, ws=wsj, stats=st)
+        out["jobs"] = {"n": 1 << 20, "arcs": int(pi.shape[0]), "readiness_ms": round(jr, 3), "pull_ms": round(jp, 3),
+                       "levels": st.rounds}
+        print(f"# stable marriage {sm_ms:.3f} ms, jobs {jr:.3f} / {jp:.3f} ms", file=sys.stderr, flush=True)
 
     if not a.no_cpu_baseline:
         import oracle

@@ -35,7 +35,7 @@ struct SchedParams {
     int can_push;
     unsigned long long seed;
     const unsigned short* mlp;   // bf16 parameter block (LLP_MLP_PARAMS), device
-    float dense_frac;            // HYBRID: dense when changed out-arcs exceed this fraction of m
+    float dense_frac;            // HYBRID: dense when changed out-arcs exceed this fraction of m, else push
     const int* plan;             // SCRIPT: round codes (device)
     long long plan_len;
 };
@@ -122,7 +122,8 @@ __device__ inline int decide_mode(const SchedParams& sp, const SchedHist& h, int
             return round_code(0, dc);
         }
         case LLP_SCHED_HYBRID:
-            return round_code((float)cl_edges > sp.dense_frac * (float)m ? 1 : 0, DCLS_NONE);
+            if ((float)cl_edges > sp.dense_frac * (float)m) return round_code(1, DCLS_NONE);
+            return round_code(sp.can_push ? 2 : 0, DCLS_NONE);
         case LLP_SCHED_RANDOM: {
             unsigned long long z = mix64d(sp.seed * 0x9E3779B97F4A7C15ull + (unsigned long long)r);
             int k = (int)(z % (unsigned long long)(sp.can_push ? 3 : 2));

@@ -38,7 +38,7 @@ int sched_params(const llp_opts& o, bool can_push, SchedParams* sp) {
     sp->delta = o.delta;
     sp->can_push = can_push ? 1 : 0;
     sp->seed = o.seed;
-    sp->dense_frac = 0.05f;
+    sp->dense_frac = 0.5f;
     if (o.sched == LLP_SCHED_SCRIPT) {
         if (o.plan_len < 0 || (o.plan_len > 0 && !o.plan)) return fail(LLP_E_ARG, "SCRIPT needs plan and plan_len");
         sp->plan = o.plan;

@@ -37,6 +37,7 @@ namespace llp {
 
 constexpr unsigned long long SM_EMPTY = ~0ull;
 constexpr int SM_NFLAG = 64;
+constexpr int SM_LOOKAHEAD = 4;   // women examined per round trip of a chain
 
 struct SCtrl {
     int done;
@@ -166,10 +167,50 @@ __global__ void k_sm_chain(SArgs a, int r) {
                 st_relaxed(&c->flag[r & (SM_NFLAG - 1)], 1);
                 break;
             }
-            ++made;
-            int w = guard(a.mpref[(long long)m * n + g], n, c->diag, 1, m, g);
-            int rk = guard(a.wrank[(long long)w * n + m], n, c->diag, 2, w, m);
-            unsigned long long key = sm_key(rk, m, g);
+            // look ahead: the next women on m's list, their ranks of m and their
+            // current best keys are independent loads; a woman whose best key
+            // already beats m's rejects him without an atomic (best only
+            // decreases), so a run of rejections costs one round trip
+            const int la = (int)min((long long)SM_LOOKAHEAD, min((long long)(n - g), cap - made));
+            int wv[SM_LOOKAHEAD];
+            unsigned long long kv[SM_LOOKAHEAD], bv[SM_LOOKAHEAD];
+#pragma unroll
+            for (int i = 0; i < SM_LOOKAHEAD; ++i) {
+                if (i < la) {
+                    wv[i] = guard(a.mpref[(long long)m * n + g + i], n, c->diag, 1, m, g + i);
+                } else {
+                    wv[i] = 0;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < SM_LOOKAHEAD; ++i) {
+                kv[i] = ~0ull;
+                bv[i] = 0ull;
+                if (i < la) {
+                    int rk = guard(a.wrank[(long long)wv[i] * n + m], n, c->diag, 2, wv[i], m);
+                    kv[i] = sm_key(rk, m, g + i);
+                    bv[i] = a.best[wv[i]];
+                }
+            }
+            int skip = 0;
+#pragma unroll
+            for (int i = 0; i < SM_LOOKAHEAD; ++i)
+                if (skip == i && i < la && bv[i] < kv[i]) skip = i + 1;
+            if (skip == la) {   // every looked-at woman holds a better man
+                g += la;
+                made += la;
+                continue;
+            }
+            g += skip;
+            made += skip + 1;
+            int w = 0;
+            unsigned long long key = 0;
+#pragma unroll
+            for (int i = 0; i < SM_LOOKAHEAD; ++i)
+                if (i == skip) {
+                    w = wv[i];
+                    key = kv[i];
+                }
             unsigned long long old = amin64(&a.best[w], key);
             if (old < key) {        // w holds a better man: m is forbidden
                 ++g;
