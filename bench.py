@@ -53,6 +53,8 @@ def parse():
     p.add_argument("--delta", type=int, default=0,
                    help="delta-bucket width for the fixed schedules (plain becomes fixed pull)")
     p.add_argument("--wgs-per-cu", type=int, default=0, help="graph sweep workgroups per CU (0 = default)")
+    p.add_argument("--nslice", type=int, default=0,
+                   help="source slices of the blocked in-CSR for dense rounds (0 = plain in-CSR)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-compare", action="store_true", help="skip the schedule comparison")
     p.add_argument("--no-batch", action="store_true", help="skip the batched-solve measurement")
@@ -166,7 +168,8 @@ def main():
     g = llpgen.rmat_graph(a.scale, seed=22)
     src = llpgen.max_outdeg_source(g)
     csr = llpgen.CSRGraph(g, weighted=True, out_weights=True)
-    dg = llp.DeviceGraph(csr)
+    blocked = (a.nslice,) + tuple(llpgen.blocked_in_csr(g, a.nslice)) if a.nslice > 0 else None
+    dg = llp.DeviceGraph(csr, blocked=blocked)
     n, m = g.n, g.m
     print(f"# graph scale {a.scale}: n={n} m={m} source={src} built in {time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
@@ -219,7 +222,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"rmat-scale{a.scale} sssp+bfs (a,b,c,d)=(.57,.19,.19,.05), relabelled, "
                                f"+hamiltonian cycle, w U[1,255] / unit, source max-outdeg, seed 22",
-                   "n": n, "m": m, "schedule": head + (f"+delta{a.delta}" if a.delta else "")},
+                   "n": n, "m": m, "schedule": head + (f"+delta{a.delta}" if a.delta else ""),
+                   "source_slices": a.nslice},
         "sssp": {"gteps": round(m / (sssp_ms * 1e-3) / 1e9, 4), "ms": round(sssp_ms, 3),
                  "rounds": s1.rounds, "edges_inspected": s1.edges_inspected, "push_edges": s1.push_edges,
                  "expand_edges": s1.expand_edges, "candidates": s1.candidates},

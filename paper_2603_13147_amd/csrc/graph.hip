@@ -63,6 +63,10 @@ struct GArgs {
     const int* out_ptr;
     const int* out_dst;
     const int* out_w;
+    int nslice;          // > 0: source-blocked in-CSR for dense rounds
+    const int* bin_ptr;
+    const int* bin_src;
+    const int* bin_w;
     int* G;
     int* stamp;
     int* cstamp;
@@ -181,6 +185,28 @@ __global__ void k_graph_validate(GArgs a) {
         }
         if (!a.unit_w && a.out_w && a.out_w[e] < 0) bad = 1;
     }
+    if (a.nslice > 0) {
+        const long long rows = (long long)a.nslice * a.n;
+        const int span = (a.n + a.nslice - 1) / a.nslice;
+        for (long long r = tid; r <= rows; r += nt) {
+            int p = a.bin_ptr[r];
+            if (r == 0 && p != 0) bad = 1;
+            if (r == rows && p != a.m) bad = 1;
+            if (r < rows) {
+                int q = a.bin_ptr[r + 1];
+                if (q < p || p < 0 || q > a.m) {
+                    bad = 1;
+                    continue;
+                }
+                const int sl = (int)(r / a.n);
+                for (int e = p; e < q; ++e) {
+                    int u = a.bin_src[e];
+                    if (u < 0 || u >= a.n || u / span != sl) bad = 1;
+                    if (!a.unit_w && a.bin_w && a.bin_w[e] < 0) bad = 1;
+                }
+            }
+        }
+    }
     if (bad) set_status(&a.ctrl->status, LLP_E_INPUT);
 }
 
@@ -223,39 +249,42 @@ __device__ __forceinline__ int dist_key(const GArgs& a, int g) { return a.jobs ?
 // Evaluate edges of the iteration: segmented max of candidates per owner,
 // advance owners by atomicMax, append changed vertices to CL.
 __device__ __forceinline__ void eval_body(const GArgs& a, const EdgeCtx& c, int r, const ListRef& out,
-                                          GShared& sh, bool& ovf, long long& nadv) {
+                                          GShared& sh, bool& ovf, long long& nadv, const int* isrc,
+                                          const int* iw) {
     const int l = lane();
+    // the segment structure is known before any gather: the tail lane of each
+    // owner's run reads the owner's state while the arcs' sources are gathered
+    int seg = c.active ? c.j : 64 + l;
+    int nseg = __shfl_down(seg, 1, LLP_WAVE);
+    bool tail = c.active && (l == 63 || nseg != seg);
+    int v = guard(c.own.x, a.n, a.ctrl->diag, 43, c.j, c.own.z);
+    int gv = tail ? a.G[v] : 0;
     int cand = 0;
     if (c.active) {
         int e = guard(c.csr, a.m, a.ctrl->diag, 41, c.own.y, c.own.z);
-        int u = guard(a.in_src[e], a.n, a.ctrl->diag, 42, e, 0);
+        int u = guard(isrc[e], a.n, a.ctrl->diag, 42, e, 0);
         if (a.jobs) {
             cand = jobs_cand(a.G[u], a.vdur[u], ovf);
         } else {
-            int w = a.unit_w ? 1 : a.in_w[e];
+            int w = a.unit_w ? 1 : iw[e];
             cand = pull_cand(a.G[u], w, ovf);
         }
     }
-    int seg = c.active ? c.j : 64 + l;
     int x = seg_incl_max(cand, seg);
-    int nseg = __shfl_down(seg, 1, LLP_WAVE);
-    bool tail = c.active && (l == 63 || nseg != seg);
     bool changed = false, advanced = false;
-    int v = guard(c.own.x, a.n, a.ctrl->diag, 43, c.j, c.own.z);
-    if (tail && x > 0) {
-        int gv = a.G[v];
-        if (x > gv) {
-            int old = amax(&a.G[v], x);
-            advanced = old < x;
-            if (advanced) changed = (amax(&a.cstamp[v], r) < r);
+    int ob = 0, od = 0;
+    if (tail && x > 0 && x > gv) {
+        int old = amax(&a.G[v], x);
+        advanced = old < x;
+        if (advanced) {
+            // the row offsets do not depend on the stamp: load them alongside
+            ob = a.out_ptr[v];
+            int oe = a.out_ptr[v + 1];
+            changed = (amax(&a.cstamp[v], r) < r);
+            od = oe - ob;
         }
     }
-    int ob = 0, od = 0;
-    if (changed) {
-        ob = a.out_ptr[v];
-        od = a.out_ptr[v + 1] - ob;
-        nadv++;
-    }
+    if (changed) nadv++;
     append(changed && od > 0, v, ob, od, &sh.ctr, out, &a.ctrl->status);
     // every advanced vertex is in CL[r] (appended now, earlier this round, or
     // carried), so its new distance bounds the list's minimum
@@ -323,14 +352,15 @@ __device__ __forceinline__ void push_body(const GArgs& a, const EdgeCtx& c, int 
         if (cand > 0 && cand > a.G[x]) {
             int old = amax(&a.G[x], cand);
             advanced = old < cand;
-            if (advanced) changed = (amax(&a.cstamp[x], r) < r);
+            if (advanced) {
+                ob = a.out_ptr[x];
+                int oe = a.out_ptr[x + 1];
+                changed = (amax(&a.cstamp[x], r) < r);
+                od = oe - ob;
+            }
         }
     }
-    if (changed) {
-        ob = a.out_ptr[x];
-        od = a.out_ptr[x + 1] - ob;
-        nadv++;
-    }
+    if (changed) nadv++;
     append(changed && od > 0, x, ob, od, &sh.ctr, out, &a.ctrl->status);
     if (out.segmin) wave_min_to_lds(advanced, dist_key(a, cand), &sh.cmin);
 }
@@ -494,10 +524,27 @@ __device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh
             a.ctrl->cand += a.n;
             a.ctrl->edges += a.m;
         }
-        DenseSrc src{a.in_ptr, a.n, a.ctrl->diag};
-        wave_range(a.m, wb, we);
         int rr = verify ? r + 1 : r;
-        for_edges(src, wb, we, own, [&](const EdgeCtx& c) { eval_body(a, c, rr, out, sh, ovf, nadv); });
+        if (a.nslice > 0 && !verify) {
+            // source-blocked rows: workgroup b walks slice b mod S (the
+            // hardware deals workgroups to the XCDs round robin), so an XCD
+            // gathers G[u] from one slice of the state
+            const int S = a.nslice;
+            const int sl = blockIdx.x % S, kb = blockIdx.x / S;
+            const int K = ((int)gridDim.x - sl + S - 1) / S;
+            const long long lo = a.bin_ptr[(long long)sl * a.n], hi = a.bin_ptr[(long long)(sl + 1) * a.n];
+            const long long W = (long long)K * GW, w = (long long)kb * GW + (threadIdx.x >> 6);
+            wb = (int)(lo + (hi - lo) * w / W);
+            we = (int)(lo + (hi - lo) * (w + 1) / W);
+            DenseSrc src{a.bin_ptr, S * a.n, a.ctrl->diag, a.n};
+            for_edges(src, wb, we, own,
+                      [&](const EdgeCtx& c) { eval_body(a, c, rr, out, sh, ovf, nadv, a.bin_src, a.bin_w); });
+        } else {
+            DenseSrc src{a.in_ptr, a.n, a.ctrl->diag, 0};
+            wave_range(a.m, wb, we);
+            for_edges(src, wb, we, own,
+                      [&](const EdgeCtx& c) { eval_body(a, c, rr, out, sh, ovf, nadv, a.in_src, a.in_w); });
+        }
     } else {
         load_segments(a.wl.seg, a.nseg, sh.cnt, sh.epre, sh.tmp, &sh.tot_edges, &sh.tot_count);
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -513,7 +560,7 @@ __device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh
         SegView sv{a.wl.ent, a.wl.cap, a.nseg, sh.cnt, sh.epre, sh.tot_edges, sh.tot_count};
         ListSrc src{sv, a.ctrl->diag};
         wave_range(sh.tot_edges, wb, we);
-        for_edges(src, wb, we, own, [&](const EdgeCtx& c) { eval_body(a, c, r, out, sh, ovf, nadv); });
+        for_edges(src, wb, we, own, [&](const EdgeCtx& c) { eval_body(a, c, r, out, sh, ovf, nadv, a.in_src, a.in_w); });
     }
     __syncthreads();
     if (threadIdx.x == 0) publish(out, sh.ctr, sh.cmin);
@@ -692,6 +739,18 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
     a.out_ptr = g->out_ptr;
     a.out_dst = g->out_dst;
     a.out_w = bfs ? nullptr : g->out_w;
+    if (g->nslice > 0) {
+        if (g->nslice > 64) return fail(LLP_E_ARG, "nslice must be in [0, 64]");
+        if (!g->bin_ptr || (g->m > 0 && !g->bin_src) || (!bfs && !jobs_dur && g->m > 0 && !g->bin_w))
+            return fail(LLP_E_ARG, "the blocked in-CSR needs bin_ptr, bin_src (and bin_w for SSSP)");
+        if ((int64_t)g->nslice * g->n >= 0x7fffffffll) return fail(LLP_E_ARG, "nslice * n must fit int32");
+        if (!jobs_dur) {
+            a.nslice = g->nslice;
+            a.bin_ptr = g->bin_ptr;
+            a.bin_src = g->bin_src;
+            a.bin_w = bfs ? nullptr : g->bin_w;
+        }
+    }
     a.G = out;
     a.source = source;
     a.unit_w = bfs ? 1 : 0;
@@ -842,6 +901,7 @@ int solve_jobs_pull(int32_t n, const int32_t* pred_ptr, const int32_t* pred_idx,
                     const int32_t* succ_ptr, const int32_t* succ_idx, int32_t* start, const llp_opts* opts,
                     int64_t E) {
     llp_graph g;
+    memset(&g, 0, sizeof(g));
     g.n = n;
     g.m = E;
     g.in_ptr = pred_ptr;

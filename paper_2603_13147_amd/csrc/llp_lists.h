@@ -104,8 +104,9 @@ struct Cursor {
 // Dense: every index v with row [ptr[v], ptr[v+1]).
 struct DenseSrc {
     const int* ptr;
-    int n;
+    int n;          // rows
     int* diag;
+    int vmod;       // > 0: row r is vertex r % vmod (slice-major blocked rows)
 
     // largest v with ptr[v] <= e (e < ptr[n]); 64-ary search, wave-uniform result
     __device__ Cursor locate(int e) const {
@@ -128,7 +129,7 @@ struct DenseSrc {
         int v = c.s + l;
         int vv = guard(v, n, diag, 14, c.s, l);
         int b = ptr[vv];
-        return make_int4(v, b, b, ptr[vv + 1] - b);
+        return make_int4(vmod > 0 ? v % vmod : v, b, b, ptr[vv + 1] - b);
     }
     __device__ Cursor advance(Cursor c, int k) const { c.s += k; return c; }
 };
@@ -209,16 +210,23 @@ __device__ inline void for_edges(const Src& src, int wb, int we, int* own_lds, B
         const bool valid = l < av;
         int last = (av < 64 ? av : 64) - 1;
         int end_last = shfl(e.z + e.w, last);
-        int limit = min(min(base + 64, we), end_last);
-        if (limit <= base) {
-            if (l == 0) record_diag(src.diag, 32, base, limit, cur.s, cur.i);
-            return;
+        if (end_last <= base) {
+            // every row of the window ends at or before base (a run of empty
+            // rows of a dense CSR): step over them
+            const int skip = __popcll(ballot(valid && e.z + e.w <= base));
+            cur = src.advance(cur, skip);
+            av = src.avail(cur);
+            e = (l < av) ? src.load(cur, l) : make_int4(0, 0, LLP_INF, 0);
+            continue;
         }
+        int limit = min(min(base + 64, we), end_last);
         own_lds[l] = 0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
+        // position base + p belongs to the last row starting at or before it:
+        // rows that start before base (or empty rows at base) vote for slot 0
         int sp = e.z - base;
-        if (valid && sp > 0 && sp < 64) atomicMax(&own_lds[sp], l);
+        if (valid && sp < 64) atomicMax(&own_lds[sp > 0 ? sp : 0], l);
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
         int j = wave_incl_max(own_lds[l]);
