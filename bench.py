@@ -53,8 +53,6 @@ def parse():
     p.add_argument("--delta", type=int, default=0,
                    help="delta-bucket width for the fixed schedules (plain becomes fixed pull)")
     p.add_argument("--wgs-per-cu", type=int, default=0, help="graph sweep workgroups per CU (0 = default)")
-    p.add_argument("--nslice", type=int, default=0,
-                   help="source slices of the blocked in-CSR for dense rounds (0 = plain in-CSR)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-compare", action="store_true", help="skip the schedule comparison")
     p.add_argument("--no-batch", action="store_true", help="skip the batched-solve measurement")
@@ -99,19 +97,20 @@ def kernel_bytes(s, weighted):
     return main, pre
 
 
-def committed_traffic():
-    """HBM bytes per phase launch of the step kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary (scaled by a plain copy's counters), or None
-    when the kernel sources changed since the counters were taken."""
+def committed_traffic(phase):
+    """HBM bytes per launch of the given phase of the step kernel from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by a plain
+    copy's counters), or None when none was taken for that phase or the kernel
+    sources changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_graph_step_rmat22_learned.traffic.json")
+    path = os.path.join(ROOT, "profiles", "k_graph_step_main_dense_rmat22_hybrid.traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     csrc = os.path.join(ROOT, "paper_2603_13147_amd", "csrc")
     h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
                                 for f in KERNEL_SOURCES)).hexdigest()[:16]
-    return rec["traffic_bytes_per_launch"] if h == rec["source_sha16"] else None
+    return rec["traffic_bytes_per_launch"] if (h == rec["source_sha16"] and rec["phase"] == phase) else None
 
 
 def time_steps(llp, dg, src, ws, dist, lev, kw, steps, warm, torch):
@@ -168,8 +167,7 @@ def main():
     g = llpgen.rmat_graph(a.scale, seed=22)
     src = llpgen.max_outdeg_source(g)
     csr = llpgen.CSRGraph(g, weighted=True, out_weights=True)
-    blocked = (a.nslice,) + tuple(llpgen.blocked_in_csr(g, a.nslice)) if a.nslice > 0 else None
-    dg = llp.DeviceGraph(csr, blocked=blocked)
+    dg = llp.DeviceGraph(csr)
     n, m = g.n, g.m
     print(f"# graph scale {a.scale}: n={n} m={m} source={src} built in {time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
@@ -203,7 +201,7 @@ def main():
     else:
         kname, kb, kt, kl = "k_graph_main (pull evaluation)", mb, mt, ml
     achieved = kb / (kt * 1e-3) / 1e9 if kt > 0 else 0.0
-    traffic = committed_traffic()
+    traffic = committed_traffic("pre" if pt > mt else "main")
     s1, s2 = recs[-1]
     sssp_ms = float(np.mean([r[0].device_ms for r in recs]))
     bfs_ms = float(np.mean([r[1].device_ms for r in recs]))
@@ -222,8 +220,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"rmat-scale{a.scale} sssp+bfs (a,b,c,d)=(.57,.19,.19,.05), relabelled, "
                                f"+hamiltonian cycle, w U[1,255] / unit, source max-outdeg, seed 22",
-                   "n": n, "m": m, "schedule": head + (f"+delta{a.delta}" if a.delta else ""),
-                   "source_slices": a.nslice},
+                   "n": n, "m": m, "schedule": head + (f"+delta{a.delta}" if a.delta else "")},
         "sssp": {"gteps": round(m / (sssp_ms * 1e-3) / 1e9, 4), "ms": round(sssp_ms, 3),
                  "rounds": s1.rounds, "edges_inspected": s1.edges_inspected, "push_edges": s1.push_edges,
                  "expand_edges": s1.expand_edges, "candidates": s1.candidates},

@@ -149,18 +149,6 @@ typedef struct {
     const int32_t* out_ptr;  /* [device] */
     const int32_t* out_dst;  /* [device] */
     const int32_t* out_w;    /* [device] or NULL (push rounds are then unavailable for SSSP) */
-    /* Optional source-blocked copy of the in-CSR for dense rounds (nslice = 0:
-       not given).  The tails are cut into nslice ranges of ceil(n / nslice)
-       ids; row (s, v) holds the in-arcs of v whose tail lies in range s, and
-       the rows are stored slice-major: bin_ptr[s * n + v] .. bin_ptr[s * n + v + 1]
-       (nslice * n + 1 offsets into bin_src / bin_w, bin_ptr[0] = 0,
-       bin_ptr[nslice * n] = m).  A dense round then walks slice s with the
-       workgroups the hardware deals to XCD s mod 8, so each XCD gathers state
-       from one range that fits its L2. */
-    int32_t nslice;
-    const int32_t* bin_ptr;  /* [device] */
-    const int32_t* bin_src;  /* [device] */
-    const int32_t* bin_w;    /* [device] or NULL (BFS) */
 } llp_graph;
 
 /* Scratch bytes a solve of this kind and size needs in opts->workspace.

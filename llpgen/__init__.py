@@ -252,13 +252,3 @@ def batch_workload(n_knap: int = 4096, n_sssp: int = 4096, seed: int = 5, sssp_n
     order = permutation(len(items), seed, tag=0x96) if items else []
     return [items[int(k)] for k in order]
 
-
-def blocked_in_csr(g: EdgeList, nslice: int = 8):
-    """Source-blocked in-CSR: tails cut into nslice ranges of ceil(n / nslice)
-    ids; rows (s, v) slice-major.  Returns (bin_ptr[nslice*n+1], bin_src[m],
-    bin_w[m]); arcs keep their input order inside a row."""
-    n = g.n
-    span = (n + nslice - 1) // nslice
-    key = (g.src // span).astype(np.int64) * n + g.dst
-    assert nslice * n < 2**31
-    return csr(nslice * n, key.astype(np.int32), g.src, g.w)

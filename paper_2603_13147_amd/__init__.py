@@ -81,9 +81,7 @@ class Opts(ctypes.Structure):
 class Graph(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64),
                 ("in_ptr", ctypes.c_void_p), ("in_src", ctypes.c_void_p), ("in_w", ctypes.c_void_p),
-                ("out_ptr", ctypes.c_void_p), ("out_dst", ctypes.c_void_p), ("out_w", ctypes.c_void_p),
-                ("nslice", ctypes.c_int32), ("bin_ptr", ctypes.c_void_p), ("bin_src", ctypes.c_void_p),
-                ("bin_w", ctypes.c_void_p)]
+                ("out_ptr", ctypes.c_void_p), ("out_dst", ctypes.c_void_p), ("out_w", ctypes.c_void_p)]
 
 
 class Instance(ctypes.Structure):
@@ -220,10 +218,9 @@ def workspace(kind, n, m, chunk=0):
 
 # ---------------------------------------------------------------- graphs
 class DeviceGraph:
-    """Device copy of a CSRGraph-like object (in_ptr/in_src/in_w, out_ptr/out_dst/out_w),
-    optionally with the source-blocked in-CSR (blocked = (nslice, bin_ptr, bin_src, bin_w))."""
+    """Device copy of a CSRGraph-like object (in_ptr/in_src/in_w, out_ptr/out_dst/out_w)."""
 
-    def __init__(self, csr, weighted=True, blocked=None):
+    def __init__(self, csr, weighted=True):
         torch = _torch()
         i32 = torch.int32
         self.n, self.m = int(csr.n), int(csr.m)
@@ -234,12 +231,6 @@ class DeviceGraph:
         self.out_dst = _dev(csr.out_dst, i32)
         ow = getattr(csr, "out_w", None)
         self.out_w = _dev(ow, i32) if (weighted and ow is not None) else None
-        self.nslice, self.bin_ptr, self.bin_src, self.bin_w = 0, None, None, None
-        if blocked is not None:
-            ns, bp, bs, bw = blocked
-            self.nslice = int(ns)
-            self.bin_ptr, self.bin_src = _dev(bp, i32), _dev(bs, i32)
-            self.bin_w = _dev(bw, i32) if (weighted and bw is not None) else None
 
     def cstruct(self):
         g = Graph()
@@ -248,9 +239,6 @@ class DeviceGraph:
                                       for t in (self.in_ptr, self.in_src, self.in_w))
         g.out_ptr, g.out_dst, g.out_w = (t.data_ptr() if t is not None else None
                                          for t in (self.out_ptr, self.out_dst, self.out_w))
-        g.nslice = self.nslice
-        g.bin_ptr, g.bin_src, g.bin_w = (t.data_ptr() if t is not None else None
-                                         for t in (self.bin_ptr, self.bin_src, self.bin_w))
         return g
 
 

@@ -63,10 +63,6 @@ struct GArgs {
     const int* out_ptr;
     const int* out_dst;
     const int* out_w;
-    int nslice;          // > 0: source-blocked in-CSR for dense rounds
-    const int* bin_ptr;
-    const int* bin_src;
-    const int* bin_w;
     int* G;
     int* stamp;
     int* cstamp;
@@ -185,28 +181,6 @@ __global__ void k_graph_validate(GArgs a) {
         }
         if (!a.unit_w && a.out_w && a.out_w[e] < 0) bad = 1;
     }
-    if (a.nslice > 0) {
-        const long long rows = (long long)a.nslice * a.n;
-        const int span = (a.n + a.nslice - 1) / a.nslice;
-        for (long long r = tid; r <= rows; r += nt) {
-            int p = a.bin_ptr[r];
-            if (r == 0 && p != 0) bad = 1;
-            if (r == rows && p != a.m) bad = 1;
-            if (r < rows) {
-                int q = a.bin_ptr[r + 1];
-                if (q < p || p < 0 || q > a.m) {
-                    bad = 1;
-                    continue;
-                }
-                const int sl = (int)(r / a.n);
-                for (int e = p; e < q; ++e) {
-                    int u = a.bin_src[e];
-                    if (u < 0 || u >= a.n || u / span != sl) bad = 1;
-                    if (!a.unit_w && a.bin_w && a.bin_w[e] < 0) bad = 1;
-                }
-            }
-        }
-    }
     if (bad) set_status(&a.ctrl->status, LLP_E_INPUT);
 }
 
@@ -249,8 +223,7 @@ __device__ __forceinline__ int dist_key(const GArgs& a, int g) { return a.jobs ?
 // Evaluate edges of the iteration: segmented max of candidates per owner,
 // advance owners by atomicMax, append changed vertices to CL.
 __device__ __forceinline__ void eval_body(const GArgs& a, const EdgeCtx& c, int r, const ListRef& out,
-                                          GShared& sh, bool& ovf, long long& nadv, const int* isrc,
-                                          const int* iw) {
+                                          GShared& sh, bool& ovf, long long& nadv) {
     const int l = lane();
     // the segment structure is known before any gather: the tail lane of each
     // owner's run reads the owner's state while the arcs' sources are gathered
@@ -262,11 +235,11 @@ __device__ __forceinline__ void eval_body(const GArgs& a, const EdgeCtx& c, int 
     int cand = 0;
     if (c.active) {
         int e = guard(c.csr, a.m, a.ctrl->diag, 41, c.own.y, c.own.z);
-        int u = guard(isrc[e], a.n, a.ctrl->diag, 42, e, 0);
+        int u = guard(a.in_src[e], a.n, a.ctrl->diag, 42, e, 0);
         if (a.jobs) {
             cand = jobs_cand(a.G[u], a.vdur[u], ovf);
         } else {
-            int w = a.unit_w ? 1 : iw[e];
+            int w = a.unit_w ? 1 : a.in_w[e];
             cand = pull_cand(a.G[u], w, ovf);
         }
     }
@@ -525,26 +498,10 @@ __device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh
             a.ctrl->edges += a.m;
         }
         int rr = verify ? r + 1 : r;
-        if (a.nslice > 0 && !verify) {
-            // source-blocked rows: workgroup b walks slice b mod S (the
-            // hardware deals workgroups to the XCDs round robin), so an XCD
-            // gathers G[u] from one slice of the state
-            const int S = a.nslice;
-            const int sl = blockIdx.x % S, kb = blockIdx.x / S;
-            const int K = ((int)gridDim.x - sl + S - 1) / S;
-            const long long lo = a.bin_ptr[(long long)sl * a.n], hi = a.bin_ptr[(long long)(sl + 1) * a.n];
-            const long long W = (long long)K * GW, w = (long long)kb * GW + (threadIdx.x >> 6);
-            wb = (int)(lo + (hi - lo) * w / W);
-            we = (int)(lo + (hi - lo) * (w + 1) / W);
-            DenseSrc src{a.bin_ptr, S * a.n, a.ctrl->diag, a.n};
-            for_edges(src, wb, we, own,
-                      [&](const EdgeCtx& c) { eval_body(a, c, rr, out, sh, ovf, nadv, a.bin_src, a.bin_w); });
-        } else {
-            DenseSrc src{a.in_ptr, a.n, a.ctrl->diag, 0};
-            wave_range(a.m, wb, we);
-            for_edges(src, wb, we, own,
-                      [&](const EdgeCtx& c) { eval_body(a, c, rr, out, sh, ovf, nadv, a.in_src, a.in_w); });
-        }
+        DenseSrc src{a.in_ptr, a.n, a.ctrl->diag, 0};
+        wave_range(a.m, wb, we);
+        for_edges(src, wb, we, own,
+                  [&](const EdgeCtx& c) { eval_body(a, c, rr, out, sh, ovf, nadv); });
     } else {
         load_segments(a.wl.seg, a.nseg, sh.cnt, sh.epre, sh.tmp, &sh.tot_edges, &sh.tot_count);
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -560,7 +517,7 @@ __device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh
         SegView sv{a.wl.ent, a.wl.cap, a.nseg, sh.cnt, sh.epre, sh.tot_edges, sh.tot_count};
         ListSrc src{sv, a.ctrl->diag};
         wave_range(sh.tot_edges, wb, we);
-        for_edges(src, wb, we, own, [&](const EdgeCtx& c) { eval_body(a, c, r, out, sh, ovf, nadv, a.in_src, a.in_w); });
+        for_edges(src, wb, we, own, [&](const EdgeCtx& c) { eval_body(a, c, r, out, sh, ovf, nadv); });
     }
     __syncthreads();
     if (threadIdx.x == 0) publish(out, sh.ctr, sh.cmin);
@@ -739,18 +696,6 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
     a.out_ptr = g->out_ptr;
     a.out_dst = g->out_dst;
     a.out_w = bfs ? nullptr : g->out_w;
-    if (g->nslice > 0) {
-        if (g->nslice > 64) return fail(LLP_E_ARG, "nslice must be in [0, 64]");
-        if (!g->bin_ptr || (g->m > 0 && !g->bin_src) || (!bfs && !jobs_dur && g->m > 0 && !g->bin_w))
-            return fail(LLP_E_ARG, "the blocked in-CSR needs bin_ptr, bin_src (and bin_w for SSSP)");
-        if ((int64_t)g->nslice * g->n >= 0x7fffffffll) return fail(LLP_E_ARG, "nslice * n must fit int32");
-        if (!jobs_dur) {
-            a.nslice = g->nslice;
-            a.bin_ptr = g->bin_ptr;
-            a.bin_src = g->bin_src;
-            a.bin_w = bfs ? nullptr : g->bin_w;
-        }
-    }
     a.G = out;
     a.source = source;
     a.unit_w = bfs ? 1 : 0;

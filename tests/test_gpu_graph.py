@@ -263,40 +263,3 @@ def test_trace_records_delta_rounds():
     assert rec["pending"].sum() > 0                      # some vertices waited for their bucket
     assert rec["out_count"].sum() > 0                    # pull rounds evaluated candidates
 
-
-@pytest.mark.parametrize("which", ["uniform4096", "rmat14", "rmat16ragged", "grid64"])
-def test_source_blocked_dense_rounds(which):
-    """Dense rounds over the source-blocked in-CSR (any slice count) reach the
-    oracle's fixpoint; the layout is validated on the device."""
-    if which == "uniform4096":
-        g = llpgen.uniform_graph(4096, 32768, 1, 100, seed=1)
-    elif which == "rmat14":
-        g = llpgen.rmat_graph(14, seed=11)
-    elif which == "rmat16ragged":
-        g = llpgen.rmat_graph(16, seed=7)
-        keep = g.m - 977
-        g = llpgen.EdgeList(g.n, g.src[:keep].copy(), g.dst[:keep].copy(), g.w[:keep].copy())
-    else:
-        g = llpgen.grid_graph(64, 64, seed=12)
-    s = llpgen.max_outdeg_source(g)
-    want = oracle.sssp(g.n, g.src, g.dst, g.w, s, bag=True)
-    wantb = oracle.bfs(g.n, g.src, g.dst, s, bag=True)
-    csr = llpgen.CSRGraph(g, weighted=True, out_weights=True)
-    for ns in (1, 3, 8):
-        dg = llp.DeviceGraph(csr, blocked=(ns,) + tuple(llpgen.blocked_in_csr(g, ns)))
-        for kw in (dict(sched=llp.SCHED_FIXED, flags=llp.DENSE | llp.VALIDATE), dict(sched=llp.SCHED_HYBRID),
-                   dict(sched=llp.SCHED_RANDOM, seed=ns)):
-            assert np.array_equal(run(llp.sssp, dg, s, **kw), want), (ns, kw)
-            assert np.array_equal(run(llp.bfs, dg, s, **kw), wantb), (ns, kw)
-
-
-def test_source_blocked_validation():
-    g = llpgen.uniform_graph(1000, 6000, 1, 100, seed=3)
-    csr = llpgen.CSRGraph(g, weighted=True, out_weights=True)
-    bp, bs, bw = llpgen.blocked_in_csr(g, 4)
-    bs = bs.copy()
-    bs[0] = (bs[0] + 500) % 1000          # a tail moved to another slice
-    dg = llp.DeviceGraph(csr, blocked=(4, bp, bs, bw))
-    with pytest.raises(llp.LLPError) as e:
-        run(llp.sssp, dg, 0, sched=llp.SCHED_FIXED, flags=llp.DENSE | llp.VALIDATE)
-    assert e.value.status == llp.E_INPUT
