@@ -277,7 +277,8 @@ def main():
     if not a.no_batch:
         items = llpgen.batch_workload(4096, 4096, seed=5)
         b = llp.Batch(items)
-        b.solve(graph=True)                      # measure, capture, instantiate
+        tune = b.autotune()                      # launch shape (threads, instances per claim)
+        b.solve(graph=True)                      # measure, capture, instantiate with the tuned shape
         torch.cuda.synchronize()
         ts = []
         for _ in range(5):
@@ -288,7 +289,9 @@ def main():
         out["batch"] = {"workload": "4096 knapsack (items U[16,256], W U[256,4096]) + 4096 sssp "
                                     "(n U[256,4096], 8n arcs + cycle, w U[1,100]), seed 5, hipGraph replay",
                         "instances": b.count, "ms": round(med, 3),
-                        "solves_per_s": round(b.count / (med * 1e-3), 1)}
+                        "solves_per_s": round(b.count / (med * 1e-3), 1),
+                        "tuned_shape": list(llp.autotune_get()),
+                        "untuned_ms": {f"{bl}x{ch}": ms for bl, ch, ms in tune}}
         print(f"# batch: {med:.3f} ms", file=sys.stderr, flush=True)
 
     if not a.no_batch:

@@ -243,7 +243,7 @@ int llp_solve_reduce(int64_t n, const uint64_t* x, uint64_t* result, const llp_o
    The return value is the first nonzero instance status.
    A first call measures the largest W and n in desc (one small readback) to
    size the LDS; opts->block / opts->chunk = 0 take the autotuned values (or
-   256 threads, 1 instance). */
+   512 threads, 1 instance). */
 typedef struct {
     int32_t kind;
     int32_t n;

@@ -212,6 +212,7 @@ struct BArgs {
     int* out_status;
     BCtrl* ctrl;
     int chunk;
+    const int* order;   // claim order (instance ids)
     int kn_w;        // LDS row capacity - 1 (max W this launch supports)
     int kn_dbuf;
     int ss_n;        // max SSSP n this launch supports
@@ -274,7 +275,7 @@ __global__ void __launch_bounds__(ch_max_block(CH)) k_batch(BArgs a) {
         __syncthreads();
         if (i0 >= a.count) break;
         const int i1 = min(i0 + a.chunk, a.count);
-        for (int i = i0; i < i1; ++i) batch_one<CH>(a, i, lds, sfl);
+        for (int i = i0; i < i1; ++i) batch_one<CH>(a, a.order[i], lds, sfl);
     }
 }
 
@@ -422,9 +423,36 @@ struct BatchPlan {
     size_t lds;
 };
 
-static int batch_ws(void** ws, const llp_opts& o) { return get_workspace(o, 256, ws); }
+// Workspace: the control block, then the claim order (int32[count]).
+static size_t batch_bytes(int64_t count) { return 256 + (size_t)(count > 0 ? count : 0) * 4; }
 
-size_t batch_workspace_bytes(int64_t) { return 256; }
+static int batch_ws(void** ws, const llp_opts& o, int64_t count) { return get_workspace(o, batch_bytes(count), ws); }
+
+size_t batch_workspace_bytes(int64_t count) { return batch_bytes(count); }
+
+// Claim order: largest estimated cost first (longest-processing-time
+// order), so the last instances to start are the short ones.  Estimated
+// cost: knapsack cells, or 20 per SSSP arc (the ratio of the two measured per
+// unit on this batch kernel).  Written to order[count] on the device.
+static int batch_order(int32_t count, const llp_instance* desc, int* order, hipStream_t st) {
+    std::vector<llp_instance> h(count);
+    int s = readback(st, desc, h.data(), sizeof(llp_instance) * (size_t)count);
+    if (s) return s;
+    std::vector<std::pair<long long, int>> key(count);
+    for (int i = 0; i < count; ++i) {
+        const llp_instance& d = h[i];
+        long long c = 0;
+        if (d.kind == LLP_KIND_KNAPSACK) c = (long long)std::max(d.n, 0) * (std::max(d.cap_or_source, 0) + 1);
+        else if (d.kind == LLP_KIND_SSSP) c = 20 * std::max<long long>(d.m, 0) + d.n;
+        key[i] = {-c, i};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int> ord(count);
+    for (int i = 0; i < count; ++i) ord[i] = key[i].second;
+    LLP_HIP(hipMemcpyAsync(order, ord.data(), sizeof(int) * (size_t)count, hipMemcpyHostToDevice, st));
+    LLP_HIP(hipStreamSynchronize(st));
+    return LLP_OK;
+}
 
 // Measure the limits over desc (one readback) and choose the launch shape.
 static int batch_plan(int32_t count, const llp_instance* desc, const llp_opts& o, BCtrl* ctrl, BatchPlan* p) {
@@ -450,7 +478,7 @@ static int batch_plan(int32_t count, const llp_instance* desc, const llp_opts& o
             if (chunk <= 0) chunk = it->second.second;
         }
     }
-    if (block <= 0) block = 256;
+    if (block <= 0) block = 512;   // the autotuner's usual choice on the mixed batch
     if (chunk <= 0) chunk = 1;
     if (block % 64 != 0 || block > 1024) return fail(LLP_E_ARG, "block must be a multiple of 64 up to 1024");
     p->block = block;
@@ -466,7 +494,7 @@ static int batch_plan(int32_t count, const llp_instance* desc, const llp_opts& o
     p->kn_dbuf = need2 <= lds_limit();
     p->lds = p->kn_dbuf ? need2 : need1;
     if (p->lds > lds_limit()) return fail(LLP_E_ARG, "instances need %zu bytes of LDS", p->lds);
-    return LLP_OK;
+    return batch_order(count, desc, (int*)((char*)ctrl + 256), st);
 }
 
 static int batch_grid(const BatchPlan& p, int count) {
@@ -496,6 +524,7 @@ static int batch_enqueue(const BatchPlan& p, int32_t count, const llp_instance* 
     a.out_words = out_words;
     a.out_status = out_status;
     a.ctrl = ctrl;
+    a.order = (const int*)((const char*)ctrl + 256);
     a.chunk = p.chunk;
     a.kn_w = p.kn_w;
     a.kn_dbuf = p.kn_dbuf;
@@ -540,7 +569,7 @@ int solve_batch(int32_t count, const llp_instance* desc, const int32_t* pool, in
     llp_opts o = opts_or_default(opts);
     hipStream_t st = (hipStream_t)o.stream;
     void* ws = nullptr;
-    s = batch_ws(&ws, o);
+    s = batch_ws(&ws, o, count);
     if (s) return s;
     BCtrl* ctrl = (BCtrl*)ws;
     BatchPlan p;
@@ -606,7 +635,7 @@ int solve_batch_graph(int32_t count, const llp_instance* desc, const int32_t* po
     llp_opts o = opts_or_default(opts);
     hipStream_t st = (hipStream_t)o.stream;
     void* ws = nullptr;
-    s = batch_ws(&ws, o);
+    s = batch_ws(&ws, o, count);
     if (s) return s;
     BCtrl* ctrl = (BCtrl*)ws;
     int32_t* status_dev = (o.flags & LLP_ASYNC) ? o.status_dev : nullptr;
@@ -690,7 +719,7 @@ int autotune_batch(int32_t count, const llp_instance* desc, const int32_t* pool,
     llp_opts o = opts_or_default(opts);
     hipStream_t st = (hipStream_t)o.stream;
     void* ws = nullptr;
-    s = batch_ws(&ws, o);
+    s = batch_ws(&ws, o, count);
     if (s) return s;
     BCtrl* ctrl = (BCtrl*)ws;
     std::string rep;
