@@ -59,6 +59,10 @@ def parse():
     p.add_argument("--heldout", action="store_true", help="also time the learned scheduler's held-out graphs")
     p.add_argument("--profile-steps", type=int, default=0,
                    help="run only this many headline steps, nothing else (for rocprofv3 runs)")
+    p.add_argument("--round-log", default="",
+                   help="with --profile-steps: write the round codes of the event-timed solves to this JSON file "
+                        "(maps a kernel trace's step launches to phases: one per push round, two per pull or "
+                        "dense round)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only copy a 1 GiB device buffer 3 times (reference for rocprofv3 byte counters)")
     return p.parse_args()
@@ -76,12 +80,22 @@ def sched_kw(llp, name, delta=0):
     return kw
 
 
-def run_step(llp, dg, src, ws, dist, lev, kw, timing):
+def run_step(llp, dg, src, ws, dist, lev, kw, timing, log=None):
+    """One headline step (SSSP then BFS).  log: a list that receives the
+    round codes of both solves (traced with LLP_TRACE)."""
     s1, s2 = llp.Stats(), llp.Stats()
     k = dict(kw)
     k["flags"] = k.get("flags", 0) | (llp.TIMING if timing else 0)
-    llp.sssp(dg, src, out=dist, ws=ws, stats=s1, **k)
-    llp.bfs(dg, src, out=lev, ws=ws, stats=s2, **k)
+    if log is None:
+        llp.sssp(dg, src, out=dist, ws=ws, stats=s1, **k)
+        llp.bfs(dg, src, out=lev, ws=ws, stats=s2, **k)
+        return s1, s2
+    k["flags"] |= llp.TRACE
+    for name, fn, out, st in (("sssp", llp.sssp, dist, s1), ("bfs", llp.bfs, lev, s2)):
+        trace = llp.trace_buffer(8192)
+        fn(dg, src, out=out, ws=ws, stats=st, trace=trace, **k)
+        rec = llp.trace_records(trace, int(st.rounds))
+        log.append({"solve": name, "modes": [int(c) for c in rec["mode"]]})
     return s1, s2
 
 
@@ -103,19 +117,21 @@ def committed_traffic(phase):
     copy's counters), or None when none was taken for that phase or the kernel
     sources changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_graph_step_main_dense_rmat22_hybrid.traffic.json")
+    path = os.path.join(ROOT, "profiles", "k_graph_step_rmat22_hybrid.traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     csrc = os.path.join(ROOT, "paper_2603_13147_amd", "csrc")
     h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
                                 for f in KERNEL_SOURCES)).hexdigest()[:16]
-    return rec["traffic_bytes_per_launch"] if (h == rec["source_sha16"] and rec["phase"] == phase) else None
+    ph = rec.get("phases", {}).get(phase)
+    return ph["traffic_bytes_per_launch"] if (h == rec["source_sha16"] and ph) else None
 
 
-def time_steps(llp, dg, src, ws, dist, lev, kw, steps, warm, torch):
+def time_steps(llp, dg, src, ws, dist, lev, kw, steps, warm, torch, log=None):
     """Wall time per step over `steps` steps without per-launch events, then
-    the same number of steps with LLP_TIMING for the kernel counters."""
+    the same number of steps with LLP_TIMING for the kernel counters (their
+    round codes go to `log` when given)."""
     for _ in range(warm):
         run_step(llp, dg, src, ws, dist, lev, kw, False)
     torch.cuda.synchronize()
@@ -124,7 +140,7 @@ def time_steps(llp, dg, src, ws, dist, lev, kw, steps, warm, torch):
         run_step(llp, dg, src, ws, dist, lev, kw, False)
     torch.cuda.synchronize()
     t = (time.perf_counter() - t1) / steps
-    recs = [run_step(llp, dg, src, ws, dist, lev, kw, True) for _ in range(steps)]
+    recs = [run_step(llp, dg, src, ws, dist, lev, kw, True, log) for _ in range(steps)]
     torch.cuda.synchronize()
     return t, recs
 
@@ -180,7 +196,11 @@ def main():
         kw["chunk"] = a.wgs_per_cu
     steps = a.profile_steps or a.steps
     warm = 0 if a.profile_steps else a.warmup
-    step_s, recs = time_steps(llp, dg, src, ws, dist, lev, kw, steps, warm, torch)
+    log = [] if (a.profile_steps and a.round_log) else None
+    step_s, recs = time_steps(llp, dg, src, ws, dist, lev, kw, steps, warm, torch, log)
+    if log is not None:
+        with open(a.round_log, "w") as f:
+            json.dump(log, f)
     value = 2 * m / step_s / 1e9
     print(f"# headline {head}: {step_s * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
 

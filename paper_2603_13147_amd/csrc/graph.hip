@@ -185,10 +185,22 @@ __global__ void k_graph_validate(GArgs a) {
 }
 
 // --------------------------------------------------------------- helpers
+// Dense rounds evaluate rows in blocks of at most DBLK arcs (every row of up
+// to DBLK in-arcs lies in one block; a row of at most DSHORT arcs is reduced
+// by one lane, a longer one by the whole wave), rows of up to DLONG in-arcs
+// are evaluated by one wave, longer rows are split between waves by arc range.
+constexpr int DBLK = 512;     // arcs per block: 8 per lane
+constexpr int DSHORT = 64;    // longest row reduced by a single lane
+constexpr int DLONG = 4096;   // longest row evaluated by a single wave
+
 struct GShared {
     int cnt[MAX_SEG];
     int epre[MAX_SEG + 1];
-    int own[GW][64];
+    union {
+        int own[GW][64];      // list iterator: owner slots
+        int dcb[GW][DBLK];    // dense blocks: candidate of each arc
+        int pw[GW][4][64];    // push blocks: entry start, source value, row base, duration
+    };
     unsigned long long ctr;    // appends to the phase's main output list
     unsigned long long cctr;   // PRE in pull rounds: entries carried into CL[r]
     int cmin;                  // smallest distance appended to CL[r] by this workgroup
@@ -264,6 +276,320 @@ __device__ __forceinline__ void eval_body(const GArgs& a, const EdgeCtx& c, int 
     if (out.segmin) wave_min_to_lds(advanced, dist_key(a, x), &sh.cmin);
 }
 
+// Candidates of N in-arcs with sources u[] (valid indices) and weights w[]:
+// all gathers are issued before any result is used; inactive arcs (act
+// false) give 0.
+template <int N>
+__device__ __forceinline__ void arc_cands(const GArgs& a, const int* u, const int* w, const bool* act, int* c,
+                                          bool& ovf) {
+    int gu[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) gu[j] = a.G[u[j]];
+    if (a.jobs) {
+        int du[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) du[j] = a.vdur[u[j]];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            bool o = false;
+            const int x = jobs_cand(gu[j], du[j], o);
+            c[j] = act[j] ? x : 0;
+            ovf |= act[j] && o;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            bool o = false;
+            const int x = pull_cand(gu[j], w[j], o);
+            c[j] = act[j] ? x : 0;
+            ovf |= act[j] && o;
+        }
+    }
+}
+
+// State of rows v .. v+63, one per lane: in-row bounds, value, out-row bounds.
+struct RowWin {
+    int pl, pn, g, ob, oe;
+};
+
+__device__ __forceinline__ RowWin load_rows(const GArgs& a, int v) {
+    RowWin w{0, 0, 0, 0, 0};
+    const int x = v + lane();
+    if (x < a.n) {
+        w.pl = a.in_ptr[x];
+        w.pn = a.in_ptr[x + 1];
+        w.g = a.G[x];
+        w.ob = a.out_ptr[x];
+        w.oe = a.out_ptr[x + 1];
+    }
+    return w;
+}
+
+// Advance index v to x if it improves on gv (lane 0's values).  whole: this
+// wave saw every in-arc of v in this phase and is its only writer, so the
+// value is stored and v appended directly; otherwise atomicMax, and the stamp
+// decides which advancing wave appends v.
+__device__ __forceinline__ void row_advance(const GArgs& a, int r, int v, int x, int gv, int ob, int oe, bool whole,
+                                            const ListRef& out, GShared& sh, long long& nadv, int& lmin) {
+    bool changed = false, advanced = false;
+    if (lane() == 0 && x > 0 && x > gv) {
+        if (whole) {
+            __hip_atomic_store(&a.G[v], x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            advanced = changed = true;
+        } else {
+            advanced = amax(&a.G[v], x) < x;
+            if (advanced) changed = amax(&a.cstamp[v], r) < r;
+        }
+    }
+    if (changed) nadv++;
+    if (advanced) lmin = min(lmin, dist_key(a, x));
+    append(changed && oe > ob, v, ob, oe - ob, &sh.ctr, out, &a.ctrl->status);
+}
+
+// Wave-wide evaluation of in-arcs [lo, hi) of row v (8 arcs per lane per
+// iteration); returns the maximum candidate in every lane.
+__device__ __forceinline__ int row_max(const GArgs& a, int lo, int hi, bool& ovf) {
+    const int l = lane();
+    const bool weighted = !a.unit_w && !a.jobs;
+    int x = 0;
+    bool bad = false;
+    for (int b = lo; b < hi; b += DBLK) {
+        // every load of the chunk is issued before any loaded index is checked
+        int u[8], w[8], c[8];
+        bool act[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int i = b + l + 64 * j;
+            act[j] = i < hi;
+            const int e = act[j] ? clampi(i, a.m, bad) : 0;
+            u[j] = act[j] ? __builtin_nontemporal_load(a.in_src + e) : 0;
+            w[j] = (act[j] && weighted) ? __builtin_nontemporal_load(a.in_w + e) : 1;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) u[j] = clampi(u[j], a.n, bad);
+        arc_cands<8>(a, u, w, act, c, ovf);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) x = max(x, c[j]);
+    }
+    if (bad) record_diag(a.ctrl->diag, 44, lo, hi, a.m, a.n);
+    return wave_max(x);
+}
+
+// Dense evaluation of one wave's arc range [wb, we): every row whose first
+// in-arc lies in the range (rows of up to DLONG arcs are evaluated whole,
+// even past we) and the part inside the range of any longer row.
+__device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef& out, GShared& sh, int* cb,
+                           bool& ovf, long long& nadv, int& lmin) {
+    if (wb >= we) return;
+    const int l = lane();
+    DenseSrc ds{a.in_ptr, a.n, a.ctrl->diag, 0};
+    int v = ds.locate(wb).s;
+    RowWin R = load_rows(a, v);
+    bool first = true;
+    while (v < a.n) {
+        const int P0 = shfl(R.pl, 0), P1 = shfl(R.pn, 0);
+        if (P0 >= we) break;
+        const int d0 = P1 - P0;
+        if (first && P0 < wb) {
+            // row v starts in an earlier wave's range: only a long row has a part here
+            first = false;
+            const RowWin Rn = load_rows(a, v + 1);
+            if (d0 > DLONG) {
+                const int x = row_max(a, wb, min(we, P1), ovf);
+                row_advance(a, r, v, x, shfl(R.g, 0), shfl(R.ob, 0), shfl(R.oe, 0), false, out, sh, nadv, lmin);
+            }
+            R = Rn;
+            ++v;
+            continue;
+        }
+        first = false;
+        if (d0 > DBLK) {
+            const RowWin Rn = load_rows(a, v + 1);
+            const int hi = d0 <= DLONG ? P1 : min(we, P1);
+            const int x = row_max(a, P0, hi, ovf);
+            row_advance(a, r, v, x, shfl(R.g, 0), shfl(R.ob, 0), shfl(R.oe, 0), hi == P1, out, sh, nadv, lmin);
+            R = Rn;
+            ++v;
+            continue;
+        }
+        // a block of rows v .. v+k-1 with at most DBLK arcs, all starting
+        // inside the range
+        const bool ok = v + l < a.n && R.pl < we && R.pn - P0 <= DBLK;
+        const uint64_t stop = ~ballot(ok);
+        const int k = stop ? __ffsll((long long)stop) - 1 : 64;   // >= 1: row v qualifies
+        const int Pk = shfl(R.pn, k - 1);
+        const RowWin Rn = load_rows(a, v + k);
+        // every load of the block is issued before any loaded index is checked
+        const bool weighted = !a.unit_w && !a.jobs;
+        bool bad = false;
+        int u[8], w[8], c[8];
+        bool act[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int i = P0 + l + 64 * j;
+            act[j] = i < Pk;
+            const int e = act[j] ? clampi(i, a.m, bad) : 0;
+            u[j] = act[j] ? __builtin_nontemporal_load(a.in_src + e) : 0;
+            w[j] = (act[j] && weighted) ? __builtin_nontemporal_load(a.in_w + e) : 1;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) u[j] = clampi(u[j], a.n, bad);
+        arc_cands<8>(a, u, w, act, c, ovf);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) cb[l + 64 * j] = c[j];   // positions past the block are never read
+        if (bad) record_diag(a.ctrl->diag, 46, v, P0, Pk, a.n);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        int x = 0;
+        const int lo = R.pl - P0, hi = R.pn - P0;   // rows of the block: within [0, DBLK]
+        if (l < k && hi - lo <= DSHORT) {
+            for (int i = lo; i < hi; ++i) x = max(x, cb[i]);
+        }
+        // the block's longer rows (at most DBLK / DSHORT of them): whole wave
+        for (uint64_t big = ballot(l < k && hi - lo > DSHORT); big; big &= big - 1) {
+            const int rl = __ffsll((long long)big) - 1;
+            const int s = shfl(lo, rl), e = shfl(hi, rl);
+            int y = 0;
+            for (int i = s + l; i < e; i += 64) y = max(y, cb[i]);
+            y = wave_max(y);
+            if (l == rl) x = y;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const bool adv = l < k && x > 0 && x > R.g;
+        if (adv) {
+            __hip_atomic_store(&a.G[v + l], x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            nadv++;
+            lmin = min(lmin, dist_key(a, x));
+        }
+        append(adv && R.oe > R.ob, v + l, R.ob, R.oe - R.ob, &sh.ctr, out, &a.ctrl->status);
+        R = Rn;
+        v += k;
+    }
+}
+
+// Push over virtual edges [wb, we) of a changed list, PBLK arcs per block:
+// a block covers at most 64 entries, each lane pushes PJ arcs of it (single-
+// arc partial advances, Definition 3).  An arc finds its entry by binary
+// search over the block's entry starts in LDS.  Delta buckets: an entry at
+// distance >= hi is carried into CL[r] (by the block where it starts) and
+// none of its arcs is pushed; the test is monotone (distances only fall), so
+// an entry pushed in part is never carried.
+constexpr int PJ = 4;
+constexpr int PBLK = 64 * PJ;
+
+template <class Src>
+__device__ void push_wave(const GArgs& a, const Src& src, int wb, int we, int r, long long hi, const ListRef& out,
+                          unsigned long long* ctr, GShared& sh, int (*pw)[64], bool& ovf, long long& nadv,
+                          int& lmin) {
+    if (wb >= we) return;
+    const int l = lane();
+    Cursor cur = src.locate(wb);
+    int base = wb;
+    int av = src.avail(cur);
+    int4 e = (l < av) ? src.load(cur, l) : make_int4(0, 0, LLP_INF, 0);
+    while (base < we) {
+        if (av <= 0) {
+            if (l == 0) record_diag(a.ctrl->diag, 32, base, we, cur.s, cur.i);
+            return;
+        }
+        const bool valid = l < av;
+        const int nv = av < 64 ? av : 64;
+        const int end_last = shfl(e.z + e.w, nv - 1);
+        const int limit = min(min(base + PBLK, we), end_last);
+        if (limit <= base) {              // inconsistent list: record and stop this wave
+            if (l == 0) record_diag(a.ctrl->diag, 33, base, end_last, cur.s, cur.i);
+            return;
+        }
+        const int done = __popcll(ballot(valid && e.z + e.w <= limit));
+        const Cursor nxt = src.advance(cur, done);
+        int nav = 0;
+        int4 ne = make_int4(0, 0, LLP_INF, 0);
+        if (limit < we) {
+            nav = src.avail(nxt);
+            if (l < nav) ne = src.load(nxt, l);
+        }
+        // the block's entries: value, carry decision, LDS tables
+        int u = 0, gu = 0, du = 0;
+        bool carry = false;
+        if (valid) {
+            u = guard(e.x, a.n, a.ctrl->diag, 61);
+            gu = ld_relaxed(&a.G[u]);
+            if (a.jobs) du = a.vdur[u];
+            carry = hi > 0 && (long long)(LLP_INF - gu) >= hi;
+        }
+        const bool put = carry && e.z >= base && e.z < limit;
+        if (put) amax(&a.cstamp[u], r);
+        append(put, e.x, e.y, e.w, ctr, out, &a.ctrl->status);
+        if (put) lmin = min(lmin, LLP_INF - gu);
+        const int kc = __popcll(ballot(put));
+        if (l == 0 && kc && a.trace) atomicAdd(&sh.carried, kc);
+        pw[0][l] = valid ? e.z : LLP_INF;
+        pw[1][l] = carry ? 0 : gu;
+        pw[2][l] = e.y - e.z;
+        pw[3][l] = du;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // arcs: entry by binary search, then every load before any check
+        int x[PJ], c[PJ], g[PJ], d[PJ], w[PJ];
+        bool bad = false;
+#pragma unroll
+        for (int j = 0; j < PJ; ++j) {
+            const int p = base + l + 64 * j;
+            g[j] = 0;
+            d[j] = 0;
+            int ei = 0;
+            if (p < limit) {
+                // last entry starting at or before p (entry 0 starts at or before base)
+                int o = 0;
+#pragma unroll
+                for (int step = 32; step >= 1; step >>= 1)
+                    if (o + step < nv && pw[0][o + step] <= p) o += step;
+                g[j] = pw[1][o];
+                d[j] = pw[3][o];
+                ei = clampi(p + pw[2][o], a.m, bad);
+            }
+            x[j] = a.out_dst[ei];                          // inactive arcs read position 0
+            w[j] = (!a.unit_w && !a.jobs) ? a.out_w[ei] : 1;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int j = 0; j < PJ; ++j) {
+            x[j] = clampi(x[j], a.n, bad);
+            c[j] = g[j] <= 0 ? 0 : (a.jobs ? jobs_cand(g[j], d[j], ovf) : pull_cand(g[j], w[j], ovf));
+        }
+        if (bad) record_diag(a.ctrl->diag, 62, base, limit, nv, a.n);
+        int gx[PJ];
+#pragma unroll
+        for (int j = 0; j < PJ; ++j) gx[j] = a.G[x[j]];
+#pragma unroll
+        for (int j = 0; j < PJ; ++j) gx[j] = c[j] > 0 ? gx[j] : LLP_INF;
+#pragma unroll
+        for (int j = 0; j < PJ; ++j) {
+            bool changed = false;
+            int ob = 0, od = 0;
+            if (c[j] > gx[j]) {
+                const int old = amax(&a.G[x[j]], c[j]);
+                if (old < c[j]) {
+                    ob = a.out_ptr[x[j]];
+                    od = a.out_ptr[x[j] + 1] - ob;
+                    changed = amax(&a.cstamp[x[j]], r) < r;
+                    lmin = min(lmin, dist_key(a, c[j]));
+                }
+            }
+            if (changed) nadv++;
+            append(changed && od > 0, x[j], ob, od, ctr, out, &a.ctrl->status);
+        }
+        cur = nxt;
+        base = limit;
+        av = nav;
+        e = ne;
+    }
+}
+
 // Delta buckets: an input entry whose vertex lies at distance >= hi is not
 // expanded (or pushed from) this round but carried into CL[r].  The entry is
 // carried by the lane holding it in the iteration where it starts; every edge
@@ -301,41 +627,6 @@ __device__ __forceinline__ void expand_body(const GArgs& a, const EdgeCtx& c, in
         }
     }
     append(fresh, x, rb, d, &sh.ctr, a.wl, &a.ctrl->status);
-}
-
-// Push: single-arc partial advance of each out-neighbour (Definition 3).
-__device__ __forceinline__ void push_body(const GArgs& a, const EdgeCtx& c, int r, const ListRef& out,
-                                          GShared& sh, bool& ovf, long long& nadv, bool skip) {
-    int umine = c.mine_valid ? guard(c.mine.x, a.n, a.ctrl->diag, 61) : 0;
-    int gmine = c.mine_valid ? a.G[umine] : 0;
-    int dmine = (c.mine_valid && a.jobs) ? a.vdur[umine] : 0;
-    int gu = shfl(gmine, c.j);
-    int du = shfl(dmine, c.j);
-    bool changed = false, advanced = false;
-    int x = 0, ob = 0, od = 0, cand = 0;
-    if (c.active && !skip) {
-        int e = guard(c.csr, a.m, a.ctrl->diag, 62, c.own.y, c.own.z);
-        x = guard(a.out_dst[e], a.n, a.ctrl->diag, 63);
-        if (a.jobs) {
-            cand = jobs_cand(gu, du, ovf);
-        } else {
-            int w = a.unit_w ? 1 : a.out_w[e];
-            cand = pull_cand(gu, w, ovf);
-        }
-        if (cand > 0 && cand > a.G[x]) {
-            int old = amax(&a.G[x], cand);
-            advanced = old < cand;
-            if (advanced) {
-                ob = a.out_ptr[x];
-                int oe = a.out_ptr[x + 1];
-                changed = (amax(&a.cstamp[x], r) < r);
-                od = oe - ob;
-            }
-        }
-    }
-    if (changed) nadv++;
-    append(changed && od > 0, x, ob, od, &sh.ctr, out, &a.ctrl->status);
-    if (out.segmin) wave_min_to_lds(advanced, dist_key(a, cand), &sh.cmin);
 }
 
 __device__ __forceinline__ void wave_range(int total, int& wb, int& we) {
@@ -456,10 +747,9 @@ __device__ void pre_phase(const GArgs& a, int r, int k, GShared& sh) {
             publish(out, sh.cctr, sh.cmin);   // MAIN appends after the carried entries
         }
     } else {
-        for_edges(src, wb, we, own, [&](const EdgeCtx& c) {
-            bool skip = carry_step(a, c, r, hi, out, &sh.ctr, sh);
-            push_body(a, c, r, out, sh, ovf, nadv, skip);
-        });
+        int lmin = LLP_INF;
+        push_wave(a, src, wb, we, r, hi, out, &sh.ctr, sh, sh.pw[threadIdx.x >> 6], ovf, nadv, lmin);
+        if (out.segmin) wave_min_to_lds(true, lmin, &sh.cmin);
         __syncthreads();
         if (threadIdx.x == 0) publish(out, sh.ctr, sh.cmin);
     }
@@ -498,10 +788,10 @@ __device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh
             a.ctrl->edges += a.m;
         }
         int rr = verify ? r + 1 : r;
-        DenseSrc src{a.in_ptr, a.n, a.ctrl->diag, 0};
         wave_range(a.m, wb, we);
-        for_edges(src, wb, we, own,
-                  [&](const EdgeCtx& c) { eval_body(a, c, rr, out, sh, ovf, nadv); });
+        int lmin = LLP_INF;
+        dense_wave(a, rr, wb, we, out, sh, sh.dcb[threadIdx.x >> 6], ovf, nadv, lmin);
+        if (out.segmin) wave_min_to_lds(true, lmin, &sh.cmin);
     } else {
         load_segments(a.wl.seg, a.nseg, sh.cnt, sh.epre, sh.tmp, &sh.tot_edges, &sh.tot_count);
         if (blockIdx.x == 0 && threadIdx.x == 0) {
