@@ -479,12 +479,75 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
 constexpr int PJ = 4;
 constexpr int PBLK = 64 * PJ;
 
+// In-round continuation (push rounds without buckets): a lane that advanced
+// a target with at most CDEG out-arcs pushes that target's arcs right away
+// with its new value, up to CDEPTH steps deep, instead of leaving it to the
+// next round; targets it does not continue through are stamped and appended
+// as usual.  A continued vertex is not stamped, so if it advances again
+// later in the round its advancer appends it.  Chains (vertices of one or
+// two out-arcs) are what it shortens; through wider fan-out (a weighted
+// mesh) it spreads values that later rounds must correct, so it stops there.
+constexpr int CDEG = 2;
+constexpr int CDEPTH = 32;
+constexpr int CONT_EDGES = 1 << 20;   // rounds with at most this many arcs to push
+
+__device__ void push_continue(const GArgs& a, int r, int cv, int cg, int cob, int cod, const ListRef& out,
+                              unsigned long long* ctr, bool& ovf, long long& nadv, int& lmin) {
+    for (int d = 0; d < CDEPTH; ++d) {
+        if (!__any(cv >= 0)) return;
+        int y[CDEG], cand[CDEG], gy[CDEG];
+        bool bad = false;
+#pragma unroll
+        for (int k = 0; k < CDEG; ++k) {
+            const bool act = cv >= 0 && k < cod;
+            const int e = act ? clampi(cob + k, a.m, bad) : 0;
+            y[k] = a.out_dst[e];
+            const int w = a.unit_w ? 1 : a.out_w[e];
+            bool o = false;
+            const int cc = pull_cand(cg, w, o);
+            ovf |= act && o;
+            cand[k] = act ? cc : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < CDEG; ++k) y[k] = clampi(y[k], a.n, bad);
+#pragma unroll
+        for (int k = 0; k < CDEG; ++k) gy[k] = a.G[y[k]];
+        if (bad) record_diag(a.ctrl->diag, 64, cv, cob, cod, a.n);
+        int nv = -1, ng = 0, nob = 0, nod = 0;
+#pragma unroll
+        for (int k = 0; k < CDEG; ++k) {
+            bool changed = false;
+            int yob = 0, yod = 0;
+            if (cand[k] > 0 && cand[k] > gy[k] && amax(&a.G[y[k]], cand[k]) < cand[k]) {
+                yob = a.out_ptr[y[k]];
+                yod = a.out_ptr[y[k] + 1] - yob;
+                lmin = min(lmin, dist_key(a, cand[k]));
+                if (nv < 0 && yod > 0 && yod <= CDEG && d + 1 < CDEPTH) {
+                    nv = y[k];
+                    ng = cand[k];
+                    nob = yob;
+                    nod = yod;
+                } else {
+                    changed = amax(&a.cstamp[y[k]], r) < r;
+                }
+            }
+            if (changed) nadv++;
+            append(changed && yod > 0, y[k], yob, yod, ctr, out, &a.ctrl->status);
+        }
+        cv = nv;
+        cg = ng;
+        cob = nob;
+        cod = nod;
+    }
+}
+
 template <class Src>
 __device__ void push_wave(const GArgs& a, const Src& src, int wb, int we, int r, long long hi, const ListRef& out,
                           unsigned long long* ctr, GShared& sh, int (*pw)[64], bool& ovf, long long& nadv,
                           int& lmin) {
     if (wb >= we) return;
     const int l = lane();
+    const bool cont = hi <= 0 && !a.jobs && src.sv.total_edges <= CONT_EDGES;
     Cursor cur = src.locate(wb);
     int base = wb;
     int av = src.avail(cur);
@@ -567,6 +630,7 @@ __device__ void push_wave(const GArgs& a, const Src& src, int wb, int we, int r,
         for (int j = 0; j < PJ; ++j) gx[j] = a.G[x[j]];
 #pragma unroll
         for (int j = 0; j < PJ; ++j) gx[j] = c[j] > 0 ? gx[j] : LLP_INF;
+        int cv = -1, cg = 0, cob = 0, cod = 0;   // this lane's continuation
 #pragma unroll
         for (int j = 0; j < PJ; ++j) {
             bool changed = false;
@@ -576,13 +640,21 @@ __device__ void push_wave(const GArgs& a, const Src& src, int wb, int we, int r,
                 if (old < c[j]) {
                     ob = a.out_ptr[x[j]];
                     od = a.out_ptr[x[j] + 1] - ob;
-                    changed = amax(&a.cstamp[x[j]], r) < r;
                     lmin = min(lmin, dist_key(a, c[j]));
+                    if (cont && cv < 0 && od > 0 && od <= CDEG) {
+                        cv = x[j];
+                        cg = c[j];
+                        cob = ob;
+                        cod = od;
+                    } else {
+                        changed = amax(&a.cstamp[x[j]], r) < r;
+                    }
                 }
             }
             if (changed) nadv++;
             append(changed && od > 0, x[j], ob, od, ctr, out, &a.ctrl->status);
         }
+        if (cont) push_continue(a, r, cv, cg, cob, cod, out, ctr, ovf, nadv, lmin);
         cur = nxt;
         base = limit;
         av = nav;

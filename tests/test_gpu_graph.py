@@ -216,6 +216,33 @@ def test_verify_and_stats_and_trace():
     assert stp.push_edges >= g.m // 4 and stp.edges_inspected == 0 and stp.pre_ms > 0
 
 
+@pytest.mark.parametrize("kind", ["sssp", "bfs"])
+def test_chain_rounds(kind):
+    """A bare cycle from vertex 0: every round pushes from one vertex, and the
+    in-round continuation carries each push up to 32 further vertices along
+    the chain (about n / 33 narrow rounds in a row); the fixpoint is the oracle's
+    bit for bit and the trace has one push record per round."""
+    n = 3000
+    g = llpgen.uniform_graph(n, 0, 1, 100, seed=31)
+    _, dg = dev_graph(g)
+    want = (oracle.sssp(g.n, g.src, g.dst, g.w, 0) if kind == "sssp"
+            else oracle.bfs(g.n, g.src, g.dst, 0))
+    fn = llp.sssp if kind == "sssp" else llp.bfs
+    for kw in (dict(sched=llp.SCHED_FIXED, flags=llp.PUSH), dict(sched=llp.SCHED_HYBRID)):
+        st = llp.Stats()
+        trace = llp.trace_buffer(n + 64)
+        k = dict(kw)
+        k["flags"] = k.get("flags", 0) | llp.TRACE | llp.TIMING
+        got = run(fn, dg, 0, stats=st, trace=trace, **k)
+        assert np.array_equal(got, want), kw
+        R = int(st.rounds)
+        assert (n - 1) // 33 <= R <= n // 32 + 2
+        rec = llp.trace_records(trace, R)
+        assert rec["round"].tolist() == list(range(1, R + 1))
+        assert np.all(rec["mode"] & 3 == llp.MODE_PUSH) and np.all(rec["in_count"] == 1)
+        assert st.eval_launches == 0 and st.pre_launches == R   # one launch per push round
+
+
 DELTA_SCHEDS = [dict(sched=llp.SCHED_FIXED, delta=d) for d in (1, 16, 64, 255, 4000)] + [
     dict(sched=llp.SCHED_FIXED, flags=llp.PUSH, delta=32),
     dict(sched=llp.SCHED_RANDOM, seed=3), dict(sched=llp.SCHED_RANDOM, seed=4),
