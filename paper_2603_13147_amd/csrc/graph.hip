@@ -348,12 +348,17 @@ __device__ __forceinline__ void row_advance(const GArgs& a, int r, int v, int x,
 
 // Wave-wide evaluation of in-arcs [lo, hi) of row v (8 arcs per lane per
 // iteration); returns the maximum candidate in every lane.
-__device__ __forceinline__ int row_max(const GArgs& a, int lo, int hi, bool& ovf) {
+// cap: no candidate can exceed it (see dense_cap), so the scan stops once
+// one reaches it; gv_live: re-read the row's state before each chunk (the
+// row is split between waves, another may already have reached the cap).
+__device__ __forceinline__ int row_max(const GArgs& a, int lo, int hi, bool& ovf, int cap, int v, bool gv_live) {
     const int l = lane();
     const bool weighted = !a.unit_w && !a.jobs;
     int x = 0;
     bool bad = false;
     for (int b = lo; b < hi; b += DBLK) {
+        if (b > lo && __any(x >= cap)) break;
+        if (gv_live && cap < LLP_INF && ld_relaxed(&a.G[v]) >= cap) break;
         // every load of the chunk is issued before any loaded index is checked
         int u[8], w[8], c[8];
         bool act[8];
@@ -379,7 +384,7 @@ __device__ __forceinline__ int row_max(const GArgs& a, int lo, int hi, bool& ovf
 // in-arc lies in the range (rows of up to DLONG arcs are evaluated whole,
 // even past we) and the part inside the range of any longer row.
 __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef& out, GShared& sh, int* cb,
-                           bool& ovf, long long& nadv, int& lmin) {
+                           bool& ovf, long long& nadv, int& lmin, int cap) {
     if (wb >= we) return;
     const int l = lane();
     DenseSrc ds{a.in_ptr, a.n, a.ctrl->diag, 0};
@@ -395,7 +400,7 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
             first = false;
             const RowWin Rn = load_rows(a, v + 1);
             if (d0 > DLONG) {
-                const int x = row_max(a, wb, min(we, P1), ovf);
+                const int x = shfl(R.g, 0) >= cap ? 0 : row_max(a, wb, min(we, P1), ovf, cap, v, true);
                 row_advance(a, r, v, x, shfl(R.g, 0), shfl(R.ob, 0), shfl(R.oe, 0), false, out, sh, nadv, lmin);
             }
             R = Rn;
@@ -406,7 +411,7 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
         if (d0 > DBLK) {
             const RowWin Rn = load_rows(a, v + 1);
             const int hi = d0 <= DLONG ? P1 : min(we, P1);
-            const int x = row_max(a, P0, hi, ovf);
+            const int x = shfl(R.g, 0) >= cap ? 0 : row_max(a, P0, hi, ovf, cap, v, hi != P1);
             row_advance(a, r, v, x, shfl(R.g, 0), shfl(R.ob, 0), shfl(R.oe, 0), hi == P1, out, sh, nadv, lmin);
             R = Rn;
             ++v;
@@ -829,6 +834,22 @@ __device__ void pre_phase(const GArgs& a, int r, int k, GShared& sh) {
     if (__any(ovf) && lane() == 0) st_relaxed(&a.ctrl->ovf, 1);
 }
 
+// Bound for the dense round r of a BFS: with dmin the smallest distance in
+// CL[r-1], every vertex whose distance is not final has true distance
+// >= dmin + 1 (on a shortest path to it, the last vertex with a final
+// distance has an out-arc still to propagate, so it is in CL[r-1]), and
+// states never pass the fixpoint.  So a candidate INF - (dmin + 1) is the
+// largest any row can still take (its evaluation may stop there), and a row
+// already at or above it is final.  LLP_INF (no bound) elsewhere: weighted
+// graphs (the smallest weight is unknown), jobs, verification.
+__device__ int dense_cap(const GArgs& a, int r, GShared& sh) {
+    if (!a.unit_w || a.jobs) return LLP_INF;
+    const ListRef in = cl_of(a, r - 1);
+    if (!in.segmin) return LLP_INF;
+    const int dmin = load_segmin(in.segmin, a.nseg, &sh.tmp1);
+    return dmin < LLP_INF - 1 ? LLP_INF - (dmin + 1) : LLP_INF;
+}
+
 // --------------------------------------------------------------- MAIN
 // Round r, second phase (pull and dense rounds): evaluate WL (or every
 // vertex) and produce CL[r].  verify != 0: a dense round on the final state
@@ -862,7 +883,8 @@ __device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh
         int rr = verify ? r + 1 : r;
         wave_range(a.m, wb, we);
         int lmin = LLP_INF;
-        dense_wave(a, rr, wb, we, out, sh, sh.dcb[threadIdx.x >> 6], ovf, nadv, lmin);
+        const int cap = (verify || (r == 1 && a.warm_dense)) ? LLP_INF : dense_cap(a, r, sh);
+        dense_wave(a, rr, wb, we, out, sh, sh.dcb[threadIdx.x >> 6], ovf, nadv, lmin, cap);
         if (out.segmin) wave_min_to_lds(true, lmin, &sh.cmin);
     } else {
         load_segments(a.wl.seg, a.nseg, sh.cnt, sh.epre, sh.tmp, &sh.tot_edges, &sh.tot_count);
