@@ -351,7 +351,9 @@ __device__ __forceinline__ void row_advance(const GArgs& a, int r, int v, int x,
 // cap: no candidate can exceed it (see dense_cap), so the scan stops once
 // one reaches it; gv_live: re-read the row's state before each chunk (the
 // row is split between waves, another may already have reached the cap).
-__device__ __forceinline__ int row_max(const GArgs& a, int lo, int hi, bool& ovf, int cap, int v, bool gv_live) {
+// nins: arcs evaluated (wave-uniform).
+__device__ __forceinline__ int row_max(const GArgs& a, int lo, int hi, bool& ovf, int cap, int v, bool gv_live,
+                                       long long& nins) {
     const int l = lane();
     const bool weighted = !a.unit_w && !a.jobs;
     int x = 0;
@@ -359,6 +361,7 @@ __device__ __forceinline__ int row_max(const GArgs& a, int lo, int hi, bool& ovf
     for (int b = lo; b < hi; b += DBLK) {
         if (b > lo && __any(x >= cap)) break;
         if (gv_live && cap < LLP_INF && ld_relaxed(&a.G[v]) >= cap) break;
+        nins += min(hi - b, DBLK);
         // every load of the chunk is issued before any loaded index is checked
         int u[8], w[8], c[8];
         bool act[8];
@@ -384,7 +387,7 @@ __device__ __forceinline__ int row_max(const GArgs& a, int lo, int hi, bool& ovf
 // in-arc lies in the range (rows of up to DLONG arcs are evaluated whole,
 // even past we) and the part inside the range of any longer row.
 __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef& out, GShared& sh, int* cb,
-                           bool& ovf, long long& nadv, int& lmin, int cap) {
+                           bool& ovf, long long& nadv, int& lmin, int cap, long long& nins) {
     if (wb >= we) return;
     const int l = lane();
     DenseSrc ds{a.in_ptr, a.n, a.ctrl->diag, 0};
@@ -400,7 +403,7 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
             first = false;
             const RowWin Rn = load_rows(a, v + 1);
             if (d0 > DLONG) {
-                const int x = shfl(R.g, 0) >= cap ? 0 : row_max(a, wb, min(we, P1), ovf, cap, v, true);
+                const int x = shfl(R.g, 0) >= cap ? 0 : row_max(a, wb, min(we, P1), ovf, cap, v, true, nins);
                 row_advance(a, r, v, x, shfl(R.g, 0), shfl(R.ob, 0), shfl(R.oe, 0), false, out, sh, nadv, lmin);
             }
             R = Rn;
@@ -411,7 +414,7 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
         if (d0 > DBLK) {
             const RowWin Rn = load_rows(a, v + 1);
             const int hi = d0 <= DLONG ? P1 : min(we, P1);
-            const int x = shfl(R.g, 0) >= cap ? 0 : row_max(a, P0, hi, ovf, cap, v, hi != P1);
+            const int x = shfl(R.g, 0) >= cap ? 0 : row_max(a, P0, hi, ovf, cap, v, hi != P1, nins);
             row_advance(a, r, v, x, shfl(R.g, 0), shfl(R.ob, 0), shfl(R.oe, 0), hi == P1, out, sh, nadv, lmin);
             R = Rn;
             ++v;
@@ -423,6 +426,7 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
         const uint64_t stop = ~ballot(ok);
         const int k = stop ? __ffsll((long long)stop) - 1 : 64;   // >= 1: row v qualifies
         const int Pk = shfl(R.pn, k - 1);
+        nins += Pk - P0;
         const RowWin Rn = load_rows(a, v + k);
         // every load of the block is issued before any loaded index is checked
         const bool weighted = !a.unit_w && !a.jobs;
@@ -876,15 +880,18 @@ __device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh
     int wb, we;
     if (mode == MODE_DENSE) {
         __syncthreads();
+        const int cap = (verify || (r == 1 && a.warm_dense)) ? LLP_INF : dense_cap(a, r, sh);
         if (blockIdx.x == 0 && threadIdx.x == 0 && !verify) {
             a.ctrl->cand += a.n;
-            a.ctrl->edges += a.m;
+            if (cap == LLP_INF) a.ctrl->edges += a.m;   // with a bound, the waves count what they read
         }
         int rr = verify ? r + 1 : r;
         wave_range(a.m, wb, we);
         int lmin = LLP_INF;
-        const int cap = (verify || (r == 1 && a.warm_dense)) ? LLP_INF : dense_cap(a, r, sh);
-        dense_wave(a, rr, wb, we, out, sh, sh.dcb[threadIdx.x >> 6], ovf, nadv, lmin, cap);
+        long long nins = 0;
+        dense_wave(a, rr, wb, we, out, sh, sh.dcb[threadIdx.x >> 6], ovf, nadv, lmin, cap, nins);
+        if (cap != LLP_INF && !verify && lane() == 0 && nins)
+            atomicAdd((unsigned long long*)&a.ctrl->edges, (unsigned long long)nins);
         if (out.segmin) wave_min_to_lds(true, lmin, &sh.cmin);
     } else {
         load_segments(a.wl.seg, a.nseg, sh.cnt, sh.epre, sh.tmp, &sh.tot_edges, &sh.tot_count);
@@ -1119,10 +1126,11 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
     a.max_rounds = max_rounds;
     GCtrl h;
     memset(&h, 0, sizeof(h));
-    // step launches: at most two per round; the batch doubles up to 32
+    // step launches: at most two per round; the first batch (16) covers a
+    // typical R-MAT sweep, then the batch doubles up to 64
     const int64_t max_launches = 2 * max_rounds + 4;
     int64_t k = 0;
-    int batch = 8;
+    int batch = 16;
     int status = LLP_OK;
     std::vector<hipEvent_t> evs;     // LLP_TIMING: one pair around each step launch
     if (timing && a.plog) {
@@ -1154,7 +1162,7 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
         }
         if (o.abort_host && *o.abort_host) { status = LLP_E_ABORTED; break; }
         if (k >= max_launches) { status = LLP_E_NOT_CONVERGED; break; }
-        if (batch < 32) batch *= 2;
+        if (batch < 64) batch *= 2;
     }
     if (status == LLP_OK && h.status == 0 && (o.flags & LLP_VERIFY)) {
         hipLaunchKernelGGL(k_graph_verify, dim3(a.nseg), dim3(GB), 0, st, a, (int)h.last_round + 1);

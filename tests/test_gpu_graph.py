@@ -216,6 +216,23 @@ def test_verify_and_stats_and_trace():
     assert stp.push_edges >= g.m // 4 and stp.edges_inspected == 0 and stp.pre_ms > 0
 
 
+def test_dense_bound_counts():
+    """Dense rounds: SSSP reads every in-arc each round; a BFS dense round
+    stops long rows at the bound INF - (dmin + 1) and counts only what it
+    read, with the oracle's levels."""
+    g = llpgen.rmat_graph(14, seed=41)
+    s = llpgen.max_outdeg_source(g)
+    _, dg = dev_graph(g)
+    st = llp.Stats()
+    got = run(llp.sssp, dg, s, sched=llp.SCHED_FIXED, flags=llp.DENSE, stats=st)
+    assert np.array_equal(got, oracle.sssp(g.n, g.src, g.dst, g.w, s, bag=True))
+    assert st.edges_inspected == st.rounds * g.m
+    sb = llp.Stats()
+    got = run(llp.bfs, dg, s, sched=llp.SCHED_FIXED, flags=llp.DENSE, stats=sb)
+    assert np.array_equal(got, oracle.bfs(g.n, g.src, g.dst, s, bag=True))
+    assert 0 < sb.edges_inspected < sb.rounds * g.m
+
+
 @pytest.mark.parametrize("kind", ["sssp", "bfs"])
 def test_chain_rounds(kind):
     """A bare cycle from vertex 0: every round pushes from one vertex, and the
