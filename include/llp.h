@@ -185,7 +185,11 @@ int llp_solve_bfs(const llp_graph* g, int32_t source, int32_t* level, const llp_
    women_rank [device] int16[n*n]: women_rank[w*n + m] = rank of m for w (0 = best).
    wife [device, output] int32[n]; proposal_idx [device, output, nullable] int32[n].
    n <= 32767.  Errors: LLP_E_ARG, LLP_E_INPUT (LLP_VALIDATE: ids out of
-   range), LLP_E_INFEASIBLE (a man exhausts his list: malformed lists). */
+   range), LLP_E_INFEASIBLE (a man exhausts his list: malformed lists).
+   With the default schedule, no warm start and no chunk, n <= 8192 runs in
+   one workgroup with the matching state in LDS, from a per-solve table of
+   (woman, her rank of the man) by man and list position; the workspace then
+   holds n * n int32 for it (llp_workspace_bytes(LLP_KIND_SM, n, 0, opts)). */
 int llp_solve_sm(int32_t n, const int16_t* men_pref, const int16_t* women_rank, int32_t* wife,
                  int32_t* proposal_idx, const llp_opts* opts);
 

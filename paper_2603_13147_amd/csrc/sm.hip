@@ -61,6 +61,7 @@ struct SArgs {
     int chunk;            // proposals per thread per launch, 0 = unbounded
     int random;           // random rounds
     unsigned long long seed;
+    int* combo;           // n <= SM_LDS_MAX: [n * n] w | rank of m for w << 16, by man and list position
 };
 
 __device__ __forceinline__ unsigned long long sm_key(int rank, int man, int idx) {
@@ -229,6 +230,103 @@ __global__ void k_sm_chain(SArgs a, int r) {
     if (lane() == 0 && tot) atomicAdd((unsigned long long*)&c->proposals, (unsigned long long)tot);
 }
 
+// One workgroup runs every chain of a cold start with n <= SM_LDS_MAX:
+// best[] and the proposal indices live in LDS, so the displacement atomic and
+// the look-ahead's best-key reads stay on the CU (a chain's steps are
+// dependent; across XCDs an atomic must reach the memory side).  Thread t
+// starts men t, t + 1024, ... in turn and carries displaced men as above.
+constexpr int SM_LDS_MAX = 8192;
+constexpr int SM_LDS_THREADS = 1024;
+
+// combo[m * n + i] = w | wrank[w][m] << 16 for the i-th woman w on m's list:
+// a chain step then reads one row (woman and her rank of m together)
+// instead of a list entry and then a rank.  Grid (ceil(n / 256), n).
+__global__ void k_sm_combo(SArgs a) {
+    const int n = a.n;
+    const int m = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long long x = (long long)m * n + i;
+    const int w = guard(a.mpref[x], n, a.ctrl->diag, 4, m, i);
+    const int rk = guard(a.wrank[(long long)w * n + m], n, a.ctrl->diag, 5, w, m);
+    a.combo[x] = w | (rk << 16);
+}
+
+__global__ void __launch_bounds__(SM_LDS_THREADS) k_sm_lds(SArgs a) {
+    __shared__ unsigned long long best[SM_LDS_MAX];
+    __shared__ int gl[SM_LDS_MAX];
+    SCtrl* c = a.ctrl;
+    const int n = a.n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        best[i] = SM_EMPTY;
+        gl[i] = 0;
+    }
+    __syncthreads();
+    long long made = 0;
+    bool infeasible = false;
+    for (int t = threadIdx.x; t < n && !infeasible; t += blockDim.x) {
+        int m = t, g = 0;
+        for (;;) {
+            if (g >= n) {
+                infeasible = true;
+                break;
+            }
+            const int la = min(SM_LOOKAHEAD, n - g);
+            int wv[SM_LOOKAHEAD], cw[SM_LOOKAHEAD];
+            unsigned long long kv[SM_LOOKAHEAD], bv[SM_LOOKAHEAD];
+#pragma unroll
+            for (int i = 0; i < SM_LOOKAHEAD; ++i) cw[i] = i < la ? a.combo[(long long)m * n + g + i] : 0;
+#pragma unroll
+            for (int i = 0; i < SM_LOOKAHEAD; ++i) {
+                wv[i] = cw[i] & 0xffff;   // < n: k_sm_combo guarded it
+                kv[i] = ~0ull;
+                bv[i] = 0ull;
+                if (i < la) {
+                    kv[i] = sm_key(cw[i] >> 16, m, g + i);
+                    bv[i] = best[wv[i]];
+                }
+            }
+            int skip = 0;
+#pragma unroll
+            for (int i = 0; i < SM_LOOKAHEAD; ++i)
+                if (skip == i && i < la && bv[i] < kv[i]) skip = i + 1;
+            if (skip == la) {
+                g += la;
+                made += la;
+                continue;
+            }
+            g += skip;
+            made += skip + 1;
+            int w = 0;
+            unsigned long long key = 0;
+#pragma unroll
+            for (int i = 0; i < SM_LOOKAHEAD; ++i)
+                if (i == skip) {
+                    w = wv[i];
+                    key = kv[i];
+                }
+            const unsigned long long old = atomicMin(&best[w], key);
+            if (old < key) {
+                ++g;
+                continue;
+            }
+            atomicMax(&gl[m], g);
+            if (old == SM_EMPTY || old == key) break;
+            m = guard((int)((old >> 16) & 0xffffull), n, c->diag, 3, w, (int)(old & 0xffff));
+            g = (int)(old & 0xffffull) + 1;
+        }
+    }
+    if (infeasible) set_status(&c->status, LLP_E_INFEASIBLE);
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) a.G[i] = gl[i];
+    const long long tot = wave_sum64(made);
+    if (lane() == 0 && tot) atomicAdd((unsigned long long*)&c->proposals, (unsigned long long)tot);
+    if (threadIdx.x == 0) {
+        c->done = 1;
+        c->last_round = 1;
+    }
+}
+
 __device__ __forceinline__ unsigned long long sm_mix(unsigned long long x) {
     x += 0x9E3779B97F4A7C15ull;
     x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -290,7 +388,9 @@ static size_t sm_ws(int64_t n, SArgs* a, char* base, size_t cap) {
     int* G = cv.take<int>(n);
     int* pend = cv.take<int>(n);
     SCtrl* ctrl = cv.take<SCtrl>(1);
+    int* combo = cv.take<int>(n <= SM_LDS_MAX ? n * n : 0);
     if (a) {
+        a->combo = combo;
         a->best = best;
         a->G = G;
         a->pend = pend;
@@ -355,7 +455,13 @@ int solve_sm(int32_t n, const int16_t* men_pref, const int16_t* women_rank, int3
     int64_t r = 1;
     int batch = rounds || a.chunk > 0 ? 8 : 2;
     int status = LLP_OK;
-    for (;;) {
+    const bool lds = !rounds && a.chunk == 0 && !a.warm && n <= SM_LDS_MAX;
+    if (lds) {
+        hipLaunchKernelGGL(k_sm_combo, dim3((n + 255) / 256, n), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_sm_lds, dim3(1), dim3(SM_LDS_THREADS), 0, st, a);
+        ++r;
+    }
+    while (!lds) {
         for (int i = 0; i < batch && r <= max_rounds; ++i, ++r) {
             if (rounds) hipLaunchKernelGGL(k_sm_round, dim3(grid_for(n, blk)), dim3(blk), 0, st, a, (int)r);
             else hipLaunchKernelGGL(k_sm_chain, dim3(grid_for(n, blk)), dim3(blk), 0, st, a, (int)r);
