@@ -133,22 +133,34 @@ __device__ int sssp_wg(const int* ptr, const int* dst, const int* wgt, int n, in
                 continue;
             }
             const int gu = G[u];
-            for (int k = b; k < e; ++k) {
-                int x = dst[k], w = wgt[k];
-                if ((unsigned)x >= (unsigned)n || w < 0) {
-                    bad = true;
-                    continue;
+            for (int k0 = b; k0 < e; k0 += 8) {
+                // the arcs' loads are all issued before any is checked
+                int xs[8], ws[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int k = k0 + j < e ? k0 + j : b;
+                    xs[j] = dst[k];
+                    ws[j] = wgt[k];
                 }
-                int cand = gu - w;
-                if (cand <= 0) {
-                    ovf = true;
-                    continue;
-                }
-                if (cand > G[x]) {
-                    int old = atomicMax(&G[x], cand);
-                    if (old < cand) {
-                        atomicOr(&nxt[x >> 5], 1u << (x & 31));
-                        adv = true;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    if (k0 + j >= e) break;
+                    const int x = xs[j], w = ws[j];
+                    if ((unsigned)x >= (unsigned)n || w < 0) {
+                        bad = true;
+                        continue;
+                    }
+                    int cand = gu - w;
+                    if (cand <= 0) {
+                        ovf = true;
+                        continue;
+                    }
+                    if (cand > G[x]) {
+                        int old = atomicMax(&G[x], cand);
+                        if (old < cand) {
+                            atomicOr(&nxt[x >> 5], 1u << (x & 31));
+                            adv = true;
+                        }
                     }
                 }
             }
