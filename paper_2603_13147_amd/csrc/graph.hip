@@ -198,7 +198,7 @@ struct GShared {
     int epre[MAX_SEG + 1];
     union {
         int own[GW][64];      // list iterator: owner slots
-        int dcb[GW][DBLK];    // dense blocks: candidate of each arc
+        int dcb[GW][DBLK + 64];   // dense blocks: candidate of each arc, then the rows' starts
         int pw[GW][4][64];    // push blocks: entry start, source value, row base, duration
     };
     unsigned long long ctr;    // appends to the phase's main output list
@@ -351,7 +351,7 @@ __device__ __forceinline__ void row_advance(const GArgs& a, int r, int v, int x,
 // cap: no candidate can exceed it (see dense_cap), so the scan stops once
 // one reaches it; gv_live: re-read the row's state before each chunk (the
 // row is split between waves, another may already have reached the cap).
-// nins: arcs evaluated (wave-uniform).
+// nins: arcs evaluated (counted by lane 0).
 __device__ __forceinline__ int row_max(const GArgs& a, int lo, int hi, bool& ovf, int cap, int v, bool gv_live,
                                        long long& nins) {
     const int l = lane();
@@ -361,7 +361,7 @@ __device__ __forceinline__ int row_max(const GArgs& a, int lo, int hi, bool& ovf
     for (int b = lo; b < hi; b += DBLK) {
         if (b > lo && __any(x >= cap)) break;
         if (gv_live && cap < LLP_INF && ld_relaxed(&a.G[v]) >= cap) break;
-        nins += min(hi - b, DBLK);
+        if (l == 0) nins += min(hi - b, DBLK);
         // every load of the chunk is issued before any loaded index is checked
         int u[8], w[8], c[8];
         bool act[8];
@@ -426,8 +426,18 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
         const uint64_t stop = ~ballot(ok);
         const int k = stop ? __ffsll((long long)stop) - 1 : 64;   // >= 1: row v qualifies
         const int Pk = shfl(R.pn, k - 1);
-        nins += Pk - P0;
         const RowWin Rn = load_rows(a, v + k);
+        // rows already at the bound are final (see dense_cap): their arcs are
+        // not read; an arc finds its row by binary search over the block's
+        // row starts in LDS (only when the block holds such a row)
+        const uint64_t fin = cap < LLP_INF ? ballot(l < k && R.g >= cap) : 0ull;
+        int* rs = cb + DBLK;
+        if (fin) {
+            rs[l] = l < k ? R.pl - P0 : 0x7fffffff;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
         // every load of the block is issued before any loaded index is checked
         const bool weighted = !a.unit_w && !a.jobs;
         bool bad = false;
@@ -437,6 +447,15 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
         for (int j = 0; j < 8; ++j) {
             const int i = P0 + l + 64 * j;
             act[j] = i < Pk;
+            if (fin && act[j]) {
+                const int p = l + 64 * j;
+                int o = 0;
+#pragma unroll
+                for (int step = 32; step >= 1; step >>= 1)
+                    if (o + step < k && rs[o + step] <= p) o += step;
+                act[j] = !((fin >> o) & 1ull);
+            }
+            nins += act[j] ? 1 : 0;
             const int e = act[j] ? clampi(i, a.m, bad) : 0;
             u[j] = act[j] ? __builtin_nontemporal_load(a.in_src + e) : 0;
             w[j] = (act[j] && weighted) ? __builtin_nontemporal_load(a.in_w + e) : 1;
@@ -890,8 +909,10 @@ __device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh
         int lmin = LLP_INF;
         long long nins = 0;
         dense_wave(a, rr, wb, we, out, sh, sh.dcb[threadIdx.x >> 6], ovf, nadv, lmin, cap, nins);
-        if (cap != LLP_INF && !verify && lane() == 0 && nins)
-            atomicAdd((unsigned long long*)&a.ctrl->edges, (unsigned long long)nins);
+        if (cap != LLP_INF && !verify) {
+            const long long tot = wave_sum64(nins);
+            if (lane() == 0 && tot) atomicAdd((unsigned long long*)&a.ctrl->edges, (unsigned long long)tot);
+        }
         if (out.segmin) wave_min_to_lds(true, lmin, &sh.cmin);
     } else {
         load_segments(a.wl.seg, a.nseg, sh.cnt, sh.epre, sh.tmp, &sh.tot_edges, &sh.tot_count);
@@ -1097,6 +1118,10 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
     a.warm_dense = (o.warm_start || jobs_dur) ? 1 : 0;   // jobs: every index is a round-1 candidate
     int s = sched_params(o, bfs || jobs_dur || g->out_w != nullptr, &a.sp);
     if (s) return s;
+    // BFS dense rounds skip the rows already final (dense_cap), so they pay
+    // from a much narrower frontier: the frontier-width rule switches at m / 14
+    // (the direction-optimizing BFS threshold) instead of m / 2
+    if (bfs) a.sp.dense_frac = 1.0f / 14.0f;
 
     const int per_cu = graph_wgs_per_cu(o.chunk);
     size_t need = graph_ws(g->n, g->m, per_cu, nullptr, nullptr, 0);
