@@ -148,7 +148,7 @@ def time_steps(llp, dg, src, ws, dist, lev, kw, steps, warm, torch, log=None):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
+        print(json.dumps({"error": "the bench runs on one GPU (the sweep does not shard); --gpus above 1 is not supported",
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
