@@ -962,7 +962,10 @@ __global__ void __launch_bounds__(GB) k_graph_verify(GArgs a, int r) {
 // Overflow: a vertex still at the bottom with a reached in-neighbour has a
 // true distance >= INF.  Only run when a candidate overflowed.
 // Jobs: every completion time S[j] + dur[j] must fit int32 (always checked).
-__global__ void k_graph_ovf(GArgs a) {
+// after_done: enqueued behind a batch of step launches; does nothing unless
+// the sweep has ended without error.
+__global__ void k_graph_ovf(GArgs a, int after_done) {
+    if (after_done && (!ld_relaxed(&a.ctrl->done) || ld_relaxed(&a.ctrl->status))) return;
     const long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const long long nt = (long long)gridDim.x * blockDim.x;
     if (a.jobs) {
@@ -984,8 +987,10 @@ __global__ void k_graph_ovf(GArgs a) {
     }
 }
 
-// In place: G -> distance (INF for unreached).
-__global__ void k_graph_decode(int* G, int n) {
+// In place: G -> distance (INF for unreached).  ctrl != NULL: enqueued behind
+// a batch of step launches; does nothing unless the sweep has ended.
+__global__ void k_graph_decode(int* G, int n, const GCtrl* ctrl) {
+    if (ctrl && !ld_relaxed(&ctrl->done)) return;
     const long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const long long nt = (long long)gridDim.x * blockDim.x;
     for (long long v = tid; v < n; v += nt) {
@@ -1157,6 +1162,7 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
     int64_t k = 0;
     int batch = 16;
     int status = LLP_OK;
+    bool finished = false;           // overflow check and decode done inside the loop
     std::vector<hipEvent_t> evs;     // LLP_TIMING: one pair around each step launch
     if (timing && a.plog) {
         hipLaunchKernelGGL(k_fill_i8, dim3(launch_grid_1d(a.plog_cap)), dim3(256), 0, st, a.plog, a.plog_cap,
@@ -1177,9 +1183,21 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
                 hipLaunchKernelGGL(k_graph_step, dim3(a.nseg), dim3(GB), 0, st, a, (int)k);
             }
         }
+        // without verification, the overflow check and the decode follow
+        // the batch and act only if the sweep has ended, so one readback
+        // both sees the end and finds the output decoded
+        const bool early = !(o.flags & LLP_VERIFY);
+        if (early) {
+            hipLaunchKernelGGL(k_graph_ovf, dim3(g1), dim3(256), 0, st, a, 1);
+            if (!jobs_dur)
+                hipLaunchKernelGGL(k_graph_decode, dim3(launch_grid_1d(g->n)), dim3(256), 0, st, out, g->n,
+                                   (const GCtrl*)a.ctrl);
+            if (timing) LLP_HIP(hipEventRecord(ev1, st));
+        }
         LLP_HIP(hipGetLastError());
         s = readback(st, a.ctrl, &h, sizeof(h));
         if (s) return s;
+        if (h.done && early) finished = true;
         if (h.status) break;
         if (h.done) {
             if (h.over) status = LLP_E_NOT_CONVERGED;
@@ -1189,15 +1207,19 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
         if (k >= max_launches) { status = LLP_E_NOT_CONVERGED; break; }
         if (batch < 64) batch *= 2;
     }
-    if (status == LLP_OK && h.status == 0 && (o.flags & LLP_VERIFY)) {
-        hipLaunchKernelGGL(k_graph_verify, dim3(a.nseg), dim3(GB), 0, st, a, (int)h.last_round + 1);
+    if (!finished) {
+        if (status == LLP_OK && h.status == 0 && (o.flags & LLP_VERIFY)) {
+            hipLaunchKernelGGL(k_graph_verify, dim3(a.nseg), dim3(GB), 0, st, a, (int)h.last_round + 1);
+        }
+        if (h.status == 0) hipLaunchKernelGGL(k_graph_ovf, dim3(g1), dim3(256), 0, st, a, 0);
+        if (!jobs_dur)
+            hipLaunchKernelGGL(k_graph_decode, dim3(launch_grid_1d(g->n)), dim3(256), 0, st, out, g->n,
+                               (const GCtrl*)nullptr);
+        LLP_HIP(hipGetLastError());
+        if (timing) LLP_HIP(hipEventRecord(ev1, st));
+        s = readback(st, a.ctrl, &h, sizeof(h));
+        if (s) return s;
     }
-    if (h.status == 0) hipLaunchKernelGGL(k_graph_ovf, dim3(g1), dim3(256), 0, st, a);
-    if (!jobs_dur) hipLaunchKernelGGL(k_graph_decode, dim3(launch_grid_1d(g->n)), dim3(256), 0, st, out, g->n);
-    LLP_HIP(hipGetLastError());
-    if (timing) LLP_HIP(hipEventRecord(ev1, st));
-    s = readback(st, a.ctrl, &h, sizeof(h));
-    if (s) return s;
     if (o.stats) {
         memset(o.stats, 0, sizeof(*o.stats));
         o.stats->rounds = h.rounds;
