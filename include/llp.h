@@ -186,7 +186,7 @@ int llp_solve_bfs(const llp_graph* g, int32_t source, int32_t* level, const llp_
    wife [device, output] int32[n]; proposal_idx [device, output, nullable] int32[n].
    n <= 32767.  Errors: LLP_E_ARG, LLP_E_INPUT (LLP_VALIDATE: ids out of
    range), LLP_E_INFEASIBLE (a man exhausts his list: malformed lists).
-   With the default schedule, no warm start and no chunk, n <= 8192 runs in
+   With the default schedule, no warm start and no chunk, n <= 12288 runs in
    one workgroup with the matching state in LDS, from a per-solve table of
    (woman, her rank of the man) by man and list position; the workspace then
    holds n * n int32 for it (llp_workspace_bytes(LLP_KIND_SM, n, 0, opts)). */

@@ -235,7 +235,7 @@ __global__ void k_sm_chain(SArgs a, int r) {
 // the look-ahead's best-key reads stay on the CU (a chain's steps are
 // dependent; across XCDs an atomic must reach the memory side).  Thread t
 // starts men t, t + 1024, ... in turn and carries displaced men as above.
-constexpr int SM_LDS_MAX = 8192;
+constexpr int SM_LDS_MAX = 12288;   // 12 B of LDS per man: 144 KB
 constexpr int SM_LDS_THREADS = 1024;
 
 // combo[m * n + i] = w | wrank[w][m] << 16 for the i-th woman w on m's list:

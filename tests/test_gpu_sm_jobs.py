@@ -53,6 +53,17 @@ def test_sm_full_size_8192(kw):
     assert np.array_equal(p, want_p)
 
 
+@pytest.mark.parametrize("kw", [dict(), dict(chunk=4)], ids=["lds", "grid"])
+def test_sm_largest_lds_instance(kw):
+    """n = 12288, the largest instance the single-workgroup path takes
+    (default schedule), and the grid-wide chains on the same lists."""
+    mpref, wrank = llpgen.sm_prefs(12288, seed=8)
+    want_w, want_p = oracle.stable_marriage(mpref, wrank)
+    w, p = run_sm(mpref, wrank, **kw)
+    assert np.array_equal(w, want_w)
+    assert np.array_equal(p, want_p)
+
+
 def test_sm_same_list_worst_case():
     # every man has the same list and every woman the same ranking: the
     # proposal count is n (n + 1) / 2, the deepest displacement chains
