@@ -61,7 +61,7 @@ def test_uniform_4096_all_schedules(kw):
     assert np.array_equal(gotb, wantb)
 
 
-FAULTED_17_9 = ("faulted the GPU once (illegal address) in the first build of the sweep; the cause "
+FAULTED_17_9 = ("faulted the GPU once (illegal address) in an early version of the sweep; the cause "
                 "was not found on the CPU: an exact emulation of the list arithmetic, device probes "
                 "of the real iterator and append code on this case's lists, and a build with every "
                 "global index bounds-checked (clean at scales 15-18) showed no out-of-range access. "
