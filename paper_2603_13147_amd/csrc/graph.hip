@@ -198,7 +198,7 @@ struct GShared {
     int epre[MAX_SEG + 1];
     union {
         int own[GW][64];      // list iterator: owner slots
-        int dcb[GW][DBLK + 64];   // dense blocks: candidate of each arc, then the rows' starts
+        int dcb[GW][DBLK + 128];  // dense blocks: candidate of each arc, the rows' starts, their arc bounds
         int pw[GW][4][64];    // push blocks: entry start, source value, row base, duration
     };
     unsigned long long ctr;    // appends to the phase's main output list
@@ -325,6 +325,15 @@ __device__ __forceinline__ RowWin load_rows(const GArgs& a, int v) {
     return w;
 }
 
+// Arc bound of a row with state g in a dense round of a weighted graph: an
+// arc of weight w can improve the row only if w < d - dlo, d = LLP_INF - g
+// its current distance and dlo the smallest distance in CL[r-1] (see
+// dense_dmin).  No bound (INT_MAX) without dlo or for an unreached row.
+__device__ __forceinline__ int arc_bound(int g, int dlo) {
+    if (dlo < 0 || g <= 0) return 0x7fffffff;
+    return (LLP_INF - g) - dlo;
+}
+
 // Advance index v to x if it improves on gv (lane 0's values).  whole: this
 // wave saw every in-arc of v in this phase and is its only writer, so the
 // value is stored and v appended directly; otherwise atomicMax, and the stamp
@@ -351,9 +360,10 @@ __device__ __forceinline__ void row_advance(const GArgs& a, int r, int v, int x,
 // cap: no candidate can exceed it (see dense_cap), so the scan stops once
 // one reaches it; gv_live: re-read the row's state before each chunk (the
 // row is split between waves, another may already have reached the cap).
-// nins: arcs evaluated (counted by lane 0).
+// thr: only arcs of weight below it can improve the row (see dense_dmin);
+// the others are not gathered.  nins: arcs gathered.
 __device__ __forceinline__ int row_max(const GArgs& a, int lo, int hi, bool& ovf, int cap, int v, bool gv_live,
-                                       long long& nins) {
+                                       int thr, long long& nins) {
     const int l = lane();
     const bool weighted = !a.unit_w && !a.jobs;
     int x = 0;
@@ -361,7 +371,6 @@ __device__ __forceinline__ int row_max(const GArgs& a, int lo, int hi, bool& ovf
     for (int b = lo; b < hi; b += DBLK) {
         if (b > lo && __any(x >= cap)) break;
         if (gv_live && cap < LLP_INF && ld_relaxed(&a.G[v]) >= cap) break;
-        if (l == 0) nins += min(hi - b, DBLK);
         // every load of the chunk is issued before any loaded index is checked
         int u[8], w[8], c[8];
         bool act[8];
@@ -374,7 +383,14 @@ __device__ __forceinline__ int row_max(const GArgs& a, int lo, int hi, bool& ovf
             w[j] = (act[j] && weighted) ? __builtin_nontemporal_load(a.in_w + e) : 1;
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) u[j] = clampi(u[j], a.n, bad);
+        for (int j = 0; j < 8; ++j) {
+            if (act[j] && w[j] >= thr) {
+                act[j] = false;
+                u[j] = 0;
+            }
+            nins += act[j] ? 1 : 0;
+            u[j] = clampi(u[j], a.n, bad);
+        }
         arc_cands<8>(a, u, w, act, c, ovf);
 #pragma unroll
         for (int j = 0; j < 8; ++j) x = max(x, c[j]);
@@ -387,7 +403,7 @@ __device__ __forceinline__ int row_max(const GArgs& a, int lo, int hi, bool& ovf
 // in-arc lies in the range (rows of up to DLONG arcs are evaluated whole,
 // even past we) and the part inside the range of any longer row.
 __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef& out, GShared& sh, int* cb,
-                           bool& ovf, long long& nadv, int& lmin, int cap, long long& nins) {
+                           bool& ovf, long long& nadv, int& lmin, int cap, int dlo, long long& nins) {
     if (wb >= we) return;
     const int l = lane();
     DenseSrc ds{a.in_ptr, a.n, a.ctrl->diag, 0};
@@ -403,7 +419,8 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
             first = false;
             const RowWin Rn = load_rows(a, v + 1);
             if (d0 > DLONG) {
-                const int x = shfl(R.g, 0) >= cap ? 0 : row_max(a, wb, min(we, P1), ovf, cap, v, true, nins);
+                const int g0 = shfl(R.g, 0);
+                const int x = g0 >= cap ? 0 : row_max(a, wb, min(we, P1), ovf, cap, v, true, arc_bound(g0, dlo), nins);
                 row_advance(a, r, v, x, shfl(R.g, 0), shfl(R.ob, 0), shfl(R.oe, 0), false, out, sh, nadv, lmin);
             }
             R = Rn;
@@ -414,7 +431,8 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
         if (d0 > DBLK) {
             const RowWin Rn = load_rows(a, v + 1);
             const int hi = d0 <= DLONG ? P1 : min(we, P1);
-            const int x = shfl(R.g, 0) >= cap ? 0 : row_max(a, P0, hi, ovf, cap, v, hi != P1, nins);
+            const int g0 = shfl(R.g, 0);
+            const int x = g0 >= cap ? 0 : row_max(a, P0, hi, ovf, cap, v, hi != P1, arc_bound(g0, dlo), nins);
             row_advance(a, r, v, x, shfl(R.g, 0), shfl(R.ob, 0), shfl(R.oe, 0), hi == P1, out, sh, nadv, lmin);
             R = Rn;
             ++v;
@@ -431,9 +449,15 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
         // not read; an arc finds its row by binary search over the block's
         // row starts in LDS (only when the block holds such a row)
         const uint64_t fin = cap < LLP_INF ? ballot(l < k && R.g >= cap) : 0ull;
+        // weighted graphs: each row's arc bound (see dense_dmin), when any
+        // row of the block has one
+        const int thr = l < k ? arc_bound(R.g, dlo) : 0x7fffffff;
+        const bool lim = ballot(thr != 0x7fffffff) != 0ull;
         int* rs = cb + DBLK;
-        if (fin) {
+        int* rt = rs + 64;
+        if (fin || lim) {
             rs[l] = l < k ? R.pl - P0 : 0x7fffffff;
+            rt[l] = thr;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -441,27 +465,35 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
         // every load of the block is issued before any loaded index is checked
         const bool weighted = !a.unit_w && !a.jobs;
         bool bad = false;
-        int u[8], w[8], c[8];
+        int u[8], w[8], c[8], t[8];
         bool act[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int i = P0 + l + 64 * j;
             act[j] = i < Pk;
-            if (fin && act[j]) {
+            t[j] = 0x7fffffff;
+            if ((fin || lim) && act[j]) {
                 const int p = l + 64 * j;
                 int o = 0;
 #pragma unroll
                 for (int step = 32; step >= 1; step >>= 1)
                     if (o + step < k && rs[o + step] <= p) o += step;
                 act[j] = !((fin >> o) & 1ull);
+                t[j] = rt[o];
             }
-            nins += act[j] ? 1 : 0;
             const int e = act[j] ? clampi(i, a.m, bad) : 0;
             u[j] = act[j] ? __builtin_nontemporal_load(a.in_src + e) : 0;
             w[j] = (act[j] && weighted) ? __builtin_nontemporal_load(a.in_w + e) : 1;
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) u[j] = clampi(u[j], a.n, bad);
+        for (int j = 0; j < 8; ++j) {
+            if (act[j] && w[j] >= t[j]) {   // cannot improve its row: no gather
+                act[j] = false;
+                u[j] = 0;
+            }
+            nins += act[j] ? 1 : 0;
+            u[j] = clampi(u[j], a.n, bad);
+        }
         arc_cands<8>(a, u, w, act, c, ovf);
 #pragma unroll
         for (int j = 0; j < 8; ++j) cb[l + 64 * j] = c[j];   // positions past the block are never read
@@ -873,6 +905,21 @@ __device__ int dense_cap(const GArgs& a, int r, GShared& sh) {
     return dmin < LLP_INF - 1 ? LLP_INF - (dmin + 1) : LLP_INF;
 }
 
+// Smallest distance dlo in CL[r-1] for the arc bound of a weighted dense
+// round.  By invariant I (an arc (u, v) either satisfies d(v) <= d(u) + w
+// or has u in CL[r-1]), an arc can improve v this round only if its tail is
+// in CL[r-1], so d(u) >= dlo, and only if dlo + w < d(v): arcs failing that
+// are not gathered.  An arc skipped while its tail improves during the
+// round is seen again in the next round, the tail being listed in CL[r].
+// -1 (no bound): unit weights (dense_cap covers them), jobs, verification.
+__device__ int dense_dmin(const GArgs& a, int r, GShared& sh) {
+    if (a.unit_w || a.jobs) return -1;
+    const ListRef in = cl_of(a, r - 1);
+    if (!in.segmin) return -1;
+    const int dmin = load_segmin(in.segmin, a.nseg, &sh.tmp1);
+    return dmin < LLP_INF - 1 ? dmin : -1;
+}
+
 // --------------------------------------------------------------- MAIN
 // Round r, second phase (pull and dense rounds): evaluate WL (or every
 // vertex) and produce CL[r].  verify != 0: a dense round on the final state
@@ -899,17 +946,19 @@ __device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh
     int wb, we;
     if (mode == MODE_DENSE) {
         __syncthreads();
-        const int cap = (verify || (r == 1 && a.warm_dense)) ? LLP_INF : dense_cap(a, r, sh);
+        const bool bounded = !verify && !(r == 1 && a.warm_dense);
+        const int cap = bounded ? dense_cap(a, r, sh) : LLP_INF;
+        const int dlo = bounded ? dense_dmin(a, r, sh) : -1;
         if (blockIdx.x == 0 && threadIdx.x == 0 && !verify) {
             a.ctrl->cand += a.n;
-            if (cap == LLP_INF) a.ctrl->edges += a.m;   // with a bound, the waves count what they read
+            if (cap == LLP_INF && dlo < 0) a.ctrl->edges += a.m;   // with a bound, the waves count what they read
         }
         int rr = verify ? r + 1 : r;
         wave_range(a.m, wb, we);
         int lmin = LLP_INF;
         long long nins = 0;
-        dense_wave(a, rr, wb, we, out, sh, sh.dcb[threadIdx.x >> 6], ovf, nadv, lmin, cap, nins);
-        if (cap != LLP_INF && !verify) {
+        dense_wave(a, rr, wb, we, out, sh, sh.dcb[threadIdx.x >> 6], ovf, nadv, lmin, cap, dlo, nins);
+        if ((cap != LLP_INF || dlo >= 0) && !verify) {
             const long long tot = wave_sum64(nins);
             if (lane() == 0 && tot) atomicAdd((unsigned long long*)&a.ctrl->edges, (unsigned long long)tot);
         }
@@ -944,7 +993,7 @@ __device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh
 // slot k & 1 (PRE of the next round, or MAIN of the current one), so a push
 // round costs one launch and a pull or dense round two.  The slots
 // alternate, so no workgroup of launch k reads the slot launch k writes.
-__global__ void __launch_bounds__(GB) k_graph_step(GArgs a, int k) {
+__global__ void __launch_bounds__(GB, 4) k_graph_step(GArgs a, int k) {
     __shared__ GShared sh;
     if (ld_relaxed(&a.ctrl->done) || ld_relaxed(&a.ctrl->status)) return;
     const int ph = a.ctrl->step_phase[k & 1];

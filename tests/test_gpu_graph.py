@@ -217,16 +217,18 @@ def test_verify_and_stats_and_trace():
 
 
 def test_dense_bound_counts():
-    """Dense rounds: SSSP reads every in-arc each round; a BFS dense round
-    stops long rows at the bound INF - (dmin + 1) and counts only what it
-    read, with the oracle's levels."""
+    """Dense rounds gather only the arcs that can still improve their row:
+    SSSP skips an arc of weight w into a row at distance d when
+    dmin + w >= d (dmin the smallest distance of the previous changed list),
+    a BFS dense round stops long rows at the bound INF - (dmin + 1); both
+    count only what they gathered, and reach the oracle's fixpoint."""
     g = llpgen.rmat_graph(14, seed=41)
     s = llpgen.max_outdeg_source(g)
     _, dg = dev_graph(g)
     st = llp.Stats()
     got = run(llp.sssp, dg, s, sched=llp.SCHED_FIXED, flags=llp.DENSE, stats=st)
     assert np.array_equal(got, oracle.sssp(g.n, g.src, g.dst, g.w, s, bag=True))
-    assert st.edges_inspected == st.rounds * g.m
+    assert 0 < st.edges_inspected < st.rounds * g.m
     sb = llp.Stats()
     got = run(llp.bfs, dg, s, sched=llp.SCHED_FIXED, flags=llp.DENSE, stats=sb)
     assert np.array_equal(got, oracle.bfs(g.n, g.src, g.dst, s, bag=True))
