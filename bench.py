@@ -101,12 +101,14 @@ def run_step(llp, dg, src, ws, dist, lev, kw, timing, log=None):
 
 def kernel_bytes(s, weighted):
     """Algorithmic bytes of the MAIN (pull evaluation) and PRE (expansion / push)
-    kernels of one solve: MAIN reads per in-arc the source id, the weight
-    (SSSP) and the gathered state (12 / 8 B) and 16 B per candidate entry; PRE
-    reads 16 B per changed entry, per expansion arc the target id and its stamp
-    (8 B), per push arc the target id, weight and state (12 / 8 B)."""
+    kernels of one solve: MAIN reads per in-arc the source id and the weight
+    (SSSP; 8 / 4 B), per gathered tail state 4 B (a dense round does not
+    gather the arcs that cannot improve their row) and 16 B per candidate
+    entry; PRE reads 16 B per changed entry, per expansion arc the target id
+    and its stamp (8 B), per push arc the target id, weight and state
+    (12 / 8 B)."""
     arc = 12 if weighted else 8
-    main = arc * s.edges_inspected + 16 * s.candidates
+    main = (arc - 4) * s.edges_inspected + 4 * s.states_gathered + 16 * s.candidates
     pre = 16 * s.advances + 8 * s.expand_edges + arc * s.push_edges
     return main, pre
 

@@ -96,6 +96,8 @@ typedef struct {
     int64_t pre_launches;     /* launches of the expansion / push (PRE) kernel (LLP_TIMING) */
     float pre_ms;             /* summed duration of the PRE kernel launches (LLP_TIMING) */
     float pad;
+    int64_t states_gathered;  /* tail states read by pull rounds: edges_inspected less the arcs a dense
+                                 round proves unable to improve their row (not gathered) */
 } llp_stats;
 
 /* One record per round when LLP_TRACE is set (device buffer of trace_cap records). */

@@ -51,7 +51,7 @@ struct GCtrl {
     int step_phase[2];  // step kernel k: phase[k & 1] 0 = PRE of round step_round + 1, 1 = MAIN of step_round
     int step_round[2];
     int diag[8];        // first guard event: site, index, bound, context
-    long long rounds, cand, edges, adv, xedges, pedges;
+    long long rounds, cand, edges, adv, xedges, pedges, gath;
     SchedHist hist[2];  // scheduler history, double-buffered by round parity
 };
 
@@ -361,9 +361,9 @@ __device__ __forceinline__ void row_advance(const GArgs& a, int r, int v, int x,
 // one reaches it; gv_live: re-read the row's state before each chunk (the
 // row is split between waves, another may already have reached the cap).
 // thr: only arcs of weight below it can improve the row (see dense_dmin);
-// the others are not gathered.  nins: arcs gathered.
+// the others are not gathered.  nrd: arcs read, nins: states gathered.
 __device__ __forceinline__ int row_max(const GArgs& a, int lo, int hi, bool& ovf, int cap, int v, bool gv_live,
-                                       int thr, long long& nins) {
+                                       int thr, int& nrd, int& nins) {
     const int l = lane();
     const bool weighted = !a.unit_w && !a.jobs;
     int x = 0;
@@ -384,6 +384,7 @@ __device__ __forceinline__ int row_max(const GArgs& a, int lo, int hi, bool& ovf
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
+            nrd += act[j] ? 1 : 0;
             if (act[j] && w[j] >= thr) {
                 act[j] = false;
                 u[j] = 0;
@@ -403,7 +404,7 @@ __device__ __forceinline__ int row_max(const GArgs& a, int lo, int hi, bool& ovf
 // in-arc lies in the range (rows of up to DLONG arcs are evaluated whole,
 // even past we) and the part inside the range of any longer row.
 __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef& out, GShared& sh, int* cb,
-                           bool& ovf, long long& nadv, int& lmin, int cap, int dlo, long long& nins) {
+                           bool& ovf, long long& nadv, int& lmin, int cap, int dlo, int& nrd, int& nins) {
     if (wb >= we) return;
     const int l = lane();
     DenseSrc ds{a.in_ptr, a.n, a.ctrl->diag, 0};
@@ -420,7 +421,7 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
             const RowWin Rn = load_rows(a, v + 1);
             if (d0 > DLONG) {
                 const int g0 = shfl(R.g, 0);
-                const int x = g0 >= cap ? 0 : row_max(a, wb, min(we, P1), ovf, cap, v, true, arc_bound(g0, dlo), nins);
+                const int x = g0 >= cap ? 0 : row_max(a, wb, min(we, P1), ovf, cap, v, true, arc_bound(g0, dlo), nrd, nins);
                 row_advance(a, r, v, x, shfl(R.g, 0), shfl(R.ob, 0), shfl(R.oe, 0), false, out, sh, nadv, lmin);
             }
             R = Rn;
@@ -432,7 +433,7 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
             const RowWin Rn = load_rows(a, v + 1);
             const int hi = d0 <= DLONG ? P1 : min(we, P1);
             const int g0 = shfl(R.g, 0);
-            const int x = g0 >= cap ? 0 : row_max(a, P0, hi, ovf, cap, v, hi != P1, arc_bound(g0, dlo), nins);
+            const int x = g0 >= cap ? 0 : row_max(a, P0, hi, ovf, cap, v, hi != P1, arc_bound(g0, dlo), nrd, nins);
             row_advance(a, r, v, x, shfl(R.g, 0), shfl(R.ob, 0), shfl(R.oe, 0), hi == P1, out, sh, nadv, lmin);
             R = Rn;
             ++v;
@@ -487,6 +488,7 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
+            nrd += act[j] ? 1 : 0;
             if (act[j] && w[j] >= t[j]) {   // cannot improve its row: no gather
                 act[j] = false;
                 u[j] = 0;
@@ -951,16 +953,20 @@ __device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh
         const int dlo = bounded ? dense_dmin(a, r, sh) : -1;
         if (blockIdx.x == 0 && threadIdx.x == 0 && !verify) {
             a.ctrl->cand += a.n;
-            if (cap == LLP_INF && dlo < 0) a.ctrl->edges += a.m;   // with a bound, the waves count what they read
+            if (cap == LLP_INF && dlo < 0) {   // with a bound, the waves count what they read
+                a.ctrl->edges += a.m;
+                a.ctrl->gath += a.m;
+            }
         }
         int rr = verify ? r + 1 : r;
         wave_range(a.m, wb, we);
         int lmin = LLP_INF;
-        long long nins = 0;
-        dense_wave(a, rr, wb, we, out, sh, sh.dcb[threadIdx.x >> 6], ovf, nadv, lmin, cap, dlo, nins);
+        int nrd = 0, nins = 0;
+        dense_wave(a, rr, wb, we, out, sh, sh.dcb[threadIdx.x >> 6], ovf, nadv, lmin, cap, dlo, nrd, nins);
         if ((cap != LLP_INF || dlo >= 0) && !verify) {
-            const long long tot = wave_sum64(nins);
-            if (lane() == 0 && tot) atomicAdd((unsigned long long*)&a.ctrl->edges, (unsigned long long)tot);
+            const long long rd = wave_sum64(nrd), tot = wave_sum64(nins);
+            if (lane() == 0 && rd) atomicAdd((unsigned long long*)&a.ctrl->edges, (unsigned long long)rd);
+            if (lane() == 0 && tot) atomicAdd((unsigned long long*)&a.ctrl->gath, (unsigned long long)tot);
         }
         if (out.segmin) wave_min_to_lds(true, lmin, &sh.cmin);
     } else {
@@ -968,6 +974,7 @@ __device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             a.ctrl->cand += sh.tot_count;
             a.ctrl->edges += sh.tot_edges;
+            a.ctrl->gath += sh.tot_edges;
             a.ctrl->hist[r & 1].wl_count = sh.tot_count;
             a.ctrl->hist[r & 1].wl_edges = sh.tot_edges;
             if (a.trace && r - 1 < a.trace_cap) {
@@ -1274,6 +1281,7 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
         o.stats->rounds = h.rounds;
         o.stats->candidates = h.cand;
         o.stats->edges_inspected = h.edges;
+        o.stats->states_gathered = h.gath;
         o.stats->advances = h.adv;
         o.stats->expand_edges = h.xedges;
         o.stats->push_edges = h.pedges;

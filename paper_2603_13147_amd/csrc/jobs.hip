@@ -360,6 +360,7 @@ int solve_jobs(int32_t n, const int32_t* pred_ptr, const int32_t* pred_idx, cons
         o.stats->candidates = h.ready;
         o.stats->advances = h.ready;
         o.stats->edges_inspected = h.edges;
+        o.stats->states_gathered = h.edges;
         if (timing) {
             float ms = 0.f;
             LLP_HIP(hipEventElapsedTime(&ms, ev0, ev1));

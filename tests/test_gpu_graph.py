@@ -228,11 +228,15 @@ def test_dense_bound_counts():
     st = llp.Stats()
     got = run(llp.sssp, dg, s, sched=llp.SCHED_FIXED, flags=llp.DENSE, stats=st)
     assert np.array_equal(got, oracle.sssp(g.n, g.src, g.dst, g.w, s, bag=True))
-    assert 0 < st.edges_inspected < st.rounds * g.m
+    # every weight is read, except (when it is a long row) the source's row, whose state is the top
+    ins = int(np.count_nonzero(g.dst == s))
+    assert st.rounds * (g.m - ins) <= st.edges_inspected <= st.rounds * g.m
+    assert 0 < st.states_gathered < st.edges_inspected       # not every tail state
     sb = llp.Stats()
     got = run(llp.bfs, dg, s, sched=llp.SCHED_FIXED, flags=llp.DENSE, stats=sb)
     assert np.array_equal(got, oracle.bfs(g.n, g.src, g.dst, s, bag=True))
     assert 0 < sb.edges_inspected < sb.rounds * g.m
+    assert sb.states_gathered == sb.edges_inspected
 
 
 @pytest.mark.parametrize("kind", ["sssp", "bfs"])
