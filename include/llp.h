@@ -56,7 +56,8 @@ typedef enum {
 #define LLP_SCHED_FIXED   1u  /* the mode given by flags (LLP_PUSH / LLP_DENSE) and delta, every round */
 #define LLP_SCHED_LEARNED 2u  /* per round, the loaded MLP picks push/pull, dense/worklist and delta */
 #define LLP_SCHED_HYBRID  3u  /* per round, a frontier-width threshold: dense when the changed vertices'
-                                 out-arcs exceed half of all arcs, push otherwise (pull without out_w) */
+                                 out-arcs exceed a fraction of all arcs (SSSP 1/3, BFS 1/14, jobs 1/2),
+                                 push otherwise (pull without out_w) */
 #define LLP_SCHED_RANDOM  4u  /* per round, a seeded random mode and delta class (schedule-independence tests) */
 #define LLP_SCHED_SCRIPT  5u  /* per round, the code opts->plan[r-1] (plain after the plan ends); used to
                                  measure what a decision at a given round costs when training the scheduler */

@@ -506,7 +506,16 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
         int x = 0;
         const int lo = R.pl - P0, hi = R.pn - P0;   // rows of the block: within [0, DBLK]
         if (l < k && hi - lo <= DSHORT) {
-            for (int i = lo; i < hi; ++i) x = max(x, cb[i]);
+            // four independent maxima: four LDS reads in flight
+            int i = lo, x1 = 0, x2 = 0, x3 = 0;
+            for (; i + 4 <= hi; i += 4) {
+                x = max(x, cb[i]);
+                x1 = max(x1, cb[i + 1]);
+                x2 = max(x2, cb[i + 2]);
+                x3 = max(x3, cb[i + 3]);
+            }
+            for (; i < hi; ++i) x = max(x, cb[i]);
+            x = max(max(x, x1), max(x2, x3));
         }
         // the block's longer rows (at most DBLK / DSHORT of them): whole wave
         for (uint64_t big = ballot(l < k && hi - lo > DSHORT); big; big &= big - 1) {
@@ -1181,8 +1190,12 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
     if (s) return s;
     // BFS dense rounds skip the rows already final (dense_cap), so they pay
     // from a much narrower frontier: the frontier-width rule switches at m / 14
-    // (the direction-optimizing BFS threshold) instead of m / 2
+    // (the direction-optimizing BFS threshold) instead of m / 2; weighted
+    // dense rounds gather only the arcs that pass the arc bound (dense_dmin),
+    // and switch at m / 3 (on R-MAT 22 a dense round costs what a push of
+    // about 0.37 m arcs does)
     if (bfs) a.sp.dense_frac = 1.0f / 14.0f;
+    else if (!jobs_dur) a.sp.dense_frac = 1.0f / 3.0f;
 
     const int per_cu = graph_wgs_per_cu(o.chunk);
     size_t need = graph_ws(g->n, g->m, per_cu, nullptr, nullptr, 0);
