@@ -9,8 +9,8 @@ highest out-degree (smallest id on ties).  Synthetic, seeded (seed 22).
 
 One step = one SSSP solve + one BFS solve to the LLP fixpoint on that graph,
 inputs resident in HBM, with the headline schedule (the frontier-width
-hybrid: dense rounds when the changed vertices' out-arcs exceed half of the
-arcs, push rounds otherwise).  value = 2 m / step
+hybrid: dense rounds when the changed vertices' out-arcs exceed a third of
+the arcs for SSSP and 1/14 for BFS, push rounds otherwise).  value = 2 m / step
 time (GTEPS, every input arc counted once per solve).
 
 The JSON line also carries
@@ -173,7 +173,7 @@ def main():
     have_w = os.path.exists(wpath)
     if have_w:
         llp.set_sched_weights(np.load(wpath))
-    # headline: the frontier-width hybrid (dense above half the arcs, push below),
+    # headline: the frontier-width hybrid (dense above m/3 arcs for SSSP, m/14 for BFS),
     # the fastest schedule measured on this graph; the learned and plain
     # schedules are reported beside it
     head = a.sched if a.sched != "auto" else "hybrid"

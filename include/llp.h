@@ -90,11 +90,12 @@ typedef struct {
     int64_t edges_inspected;  /* in-arcs read by pull rounds */
     int64_t advances;         /* entries of the changed lists consumed (indices advanced) */
     int64_t expand_edges;     /* out-arcs read by successor expansion */
-    int64_t eval_launches;    /* launches of the evaluation (MAIN) kernel (LLP_TIMING) */
+    int64_t eval_launches;    /* step launches that evaluated a pull or dense round (LLP_TIMING; a dense
+                                 round is decided and evaluated in one launch) */
     float device_ms;          /* whole solve on the stream (LLP_TIMING) */
     float kernel_ms;          /* summed duration of the evaluation (MAIN) kernel launches (LLP_TIMING) */
     int64_t push_edges;       /* out-arcs read by push rounds */
-    int64_t pre_launches;     /* launches of the expansion / push (PRE) kernel (LLP_TIMING) */
+    int64_t pre_launches;     /* step launches that only expanded or pushed (LLP_TIMING) */
     float pre_ms;             /* summed duration of the PRE kernel launches (LLP_TIMING) */
     float pad;
     int64_t states_gathered;  /* tail states read by pull rounds: edges_inspected less the arcs a dense

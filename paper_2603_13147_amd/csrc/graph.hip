@@ -47,6 +47,7 @@ struct GCtrl {
     int verify_changed;
     int dbase;          // delta base width (2^floor(log2 mean weight), from a sample of the arcs)
     int over;           // the round limit was reached
+    int decoded;        // the launch that found the end decoded G in place
     int carried[2];     // entries carried by the delta filter, by round parity (traced solves)
     int step_phase[2];  // step kernel k: phase[k & 1] 0 = PRE of round step_round + 1, 1 = MAIN of step_round
     int step_round[2];
@@ -73,6 +74,7 @@ struct GArgs {
     int jobs;          // job scheduling in pull form: G = S, contribution S[p] + dur[p]
     const int* vdur;   // jobs: duration per job (the weight of every out-arc of p)
     int warm_dense;    // warm start: round 1 is dense
+    int fuse_end;      // the launch that finds the end decodes G (no verification, not jobs)
     GCtrl* ctrl;
     llp_trace_rec* trace;
     long long trace_cap;
@@ -799,8 +801,9 @@ __device__ __forceinline__ int delta_of(const GArgs& a, int code) {
 
 // --------------------------------------------------------------- PRE
 // Round r, first phase: consume CL[r-1], decide the round's code, then
-// expand into WL (pull), push (CL[r]) or nothing (dense).  k: step launch.
-__device__ void pre_phase(const GArgs& a, int r, int k, GShared& sh) {
+// expand into WL (pull) or push (CL[r]); returns the code of a dense round,
+// whose evaluation follows in the same launch, else -1.  k: step launch.
+__device__ int pre_phase(const GArgs& a, int r, int k, GShared& sh) {
     const ListRef in = cl_of(a, r - 1);
     const ListRef out = cl_of(a, r);
     load_segments(in.seg, a.nseg, sh.cnt, sh.epre, sh.tmp, &sh.tot_edges, &sh.tot_count);
@@ -815,7 +818,17 @@ __device__ void pre_phase(const GArgs& a, int r, int k, GShared& sh) {
             a.ctrl->done = 1;
             a.ctrl->last_round = r - 1;
         }
-        return;
+        // the sweep has ended: every workgroup sees it, and no other launch
+        // touches G any more, so the output is decoded here (unless a
+        // candidate overflowed: the overflow check reads the encoded states)
+        if (a.fuse_end && !ld_relaxed(&a.ctrl->ovf)) {
+            for (long long v = blockIdx.x * (long long)GB + threadIdx.x; v < a.n; v += (long long)gridDim.x * GB) {
+                const int g = a.G[v];
+                a.G[v] = g > 0 ? LLP_INF - g : LLP_INF;
+            }
+            if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->decoded = 1;
+        }
+        return -1;
     }
     if ((long long)r > a.max_rounds) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -823,7 +836,7 @@ __device__ void pre_phase(const GArgs& a, int r, int k, GShared& sh) {
             a.ctrl->done = 1;
             a.ctrl->last_round = r - 1;
         }
-        return;
+        return -1;
     }
     // schedule decision (identical in every workgroup)
     if (threadIdx.x < 64) {
@@ -850,8 +863,9 @@ __device__ void pre_phase(const GArgs& a, int r, int k, GShared& sh) {
         GCtrl* c = a.ctrl;
         c->mode = code;
         c->rounds = r;
-        // the next step launch: MAIN of this round, or PRE of the next one after a push
-        c->step_phase[(k + 1) & 1] = mode == MODE_PUSH ? 0 : 1;
+        // the next step launch: MAIN of a pull round, else PRE of the next round
+        // (a dense round is evaluated in this launch)
+        c->step_phase[(k + 1) & 1] = mode == MODE_PULL ? 1 : 0;
         c->step_round[(k + 1) & 1] = r;
         if (a.plog && k < a.plog_cap) a.plog[k] = 0;
         c->adv += sh.tot_count;
@@ -871,7 +885,7 @@ __device__ void pre_phase(const GArgs& a, int r, int k, GShared& sh) {
             a.trace[r - 1] = t;
         }
     }
-    if (mode == MODE_DENSE) return;
+    if (mode == MODE_DENSE) return code;   // evaluated by the caller in this launch
     SegView sv{in.ent, in.cap, a.nseg, sh.cnt, sh.epre, sh.tot_edges, sh.tot_count};
     ListSrc src{sv, a.ctrl->diag};
     int wb, we;
@@ -898,6 +912,7 @@ __device__ void pre_phase(const GArgs& a, int r, int k, GShared& sh) {
     }
     if (threadIdx.x == 0 && sh.carried) atomicAdd(&a.ctrl->carried[r & 1], sh.carried);
     if (__any(ovf) && lane() == 0) st_relaxed(&a.ctrl->ovf, 1);
+    return -1;
 }
 
 // Bound for the dense round r of a BFS: with dmin the smallest distance in
@@ -935,8 +950,8 @@ __device__ int dense_dmin(const GArgs& a, int r, GShared& sh) {
 // Round r, second phase (pull and dense rounds): evaluate WL (or every
 // vertex) and produce CL[r].  verify != 0: a dense round on the final state
 // that must change nothing.
-__device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh) {
-    const int code = verify ? MODE_DENSE : a.ctrl->mode;
+__device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh, int round_code) {
+    const int code = verify ? MODE_DENSE : round_code;
     const int mode = code & 3;
     if (!verify && blockIdx.x == 0 && threadIdx.x == 0) {
         a.ctrl->step_phase[(k + 1) & 1] = 0;
@@ -1006,21 +1021,30 @@ __device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh
 }
 
 // One step of the sweep: launch k runs the phase the previous launch left in
-// slot k & 1 (PRE of the next round, or MAIN of the current one), so a push
-// round costs one launch and a pull or dense round two.  The slots
-// alternate, so no workgroup of launch k reads the slot launch k writes.
+// slot k & 1 (PRE of the next round, or MAIN of the current one).  A dense
+// round is decided and evaluated in one launch (every workgroup takes the
+// same decision from the same list totals), so push and dense rounds cost
+// one launch, a pull round two.  The slots alternate, so no workgroup of
+// launch k reads the slot launch k writes.
 __global__ void __launch_bounds__(GB, 4) k_graph_step(GArgs a, int k) {
     __shared__ GShared sh;
     if (ld_relaxed(&a.ctrl->done) || ld_relaxed(&a.ctrl->status)) return;
     const int ph = a.ctrl->step_phase[k & 1];
     const int rr = a.ctrl->step_round[k & 1];
-    if (ph == 0) pre_phase(a, rr + 1, k, sh);
-    else main_phase(a, rr, 0, k, sh);
+    int r = rr, code;
+    if (ph == 0) {
+        r = rr + 1;
+        code = pre_phase(a, r, k, sh);
+        if (code < 0) return;
+    } else {
+        code = a.ctrl->mode;
+    }
+    main_phase(a, r, 0, k, sh, code);
 }
 
 __global__ void __launch_bounds__(GB) k_graph_verify(GArgs a, int r) {
     __shared__ GShared sh;
-    main_phase(a, r, 1, 0, sh);
+    main_phase(a, r, 1, 0, sh, MODE_DENSE);
 }
 
 // --------------------------------------------------------------- finish
@@ -1052,10 +1076,9 @@ __global__ void k_graph_ovf(GArgs a, int after_done) {
     }
 }
 
-// In place: G -> distance (INF for unreached).  ctrl != NULL: enqueued behind
-// a batch of step launches; does nothing unless the sweep has ended.
-__global__ void k_graph_decode(int* G, int n, const GCtrl* ctrl) {
-    if (ctrl && !ld_relaxed(&ctrl->done)) return;
+// In place: G -> distance (INF for unreached), after verification or an
+// overflow check (otherwise the step launch that finds the end decodes).
+__global__ void k_graph_decode(int* G, int n) {
     const long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     const long long nt = (long long)gridDim.x * blockDim.x;
     for (long long v = tid; v < n; v += nt) {
@@ -1186,6 +1209,7 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
     a.trace = (o.flags & LLP_TRACE) ? o.trace_dev : nullptr;
     a.trace_cap = o.trace_cap;
     a.warm_dense = (o.warm_start || jobs_dur) ? 1 : 0;   // jobs: every index is a round-1 candidate
+    a.fuse_end = (!(o.flags & LLP_VERIFY) && !jobs_dur) ? 1 : 0;
     int s = sched_params(o, bfs || jobs_dur || g->out_w != nullptr, &a.sp);
     if (s) return s;
     // BFS dense rounds skip the rows already final (dense_cap), so they pay
@@ -1252,21 +1276,19 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
                 hipLaunchKernelGGL(k_graph_step, dim3(a.nseg), dim3(GB), 0, st, a, (int)k);
             }
         }
-        // without verification, the overflow check and the decode follow
-        // the batch and act only if the sweep has ended, so one readback
-        // both sees the end and finds the output decoded
+        // without verification, the step launch that finds the end decodes
+        // the output itself (jobs: the overflow check follows the batch and
+        // acts only once the sweep has ended), so one readback both sees the
+        // end and finds the output final
         const bool early = !(o.flags & LLP_VERIFY);
         if (early) {
-            hipLaunchKernelGGL(k_graph_ovf, dim3(g1), dim3(256), 0, st, a, 1);
-            if (!jobs_dur)
-                hipLaunchKernelGGL(k_graph_decode, dim3(launch_grid_1d(g->n)), dim3(256), 0, st, out, g->n,
-                                   (const GCtrl*)a.ctrl);
+            if (jobs_dur) hipLaunchKernelGGL(k_graph_ovf, dim3(g1), dim3(256), 0, st, a, 1);
             if (timing) LLP_HIP(hipEventRecord(ev1, st));
         }
         LLP_HIP(hipGetLastError());
         s = readback(st, a.ctrl, &h, sizeof(h));
         if (s) return s;
-        if (h.done && early) finished = true;
+        if (h.done && early && (jobs_dur || h.decoded)) finished = true;
         if (h.status) break;
         if (h.done) {
             if (h.over) status = LLP_E_NOT_CONVERGED;
@@ -1282,8 +1304,7 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
         }
         if (h.status == 0) hipLaunchKernelGGL(k_graph_ovf, dim3(g1), dim3(256), 0, st, a, 0);
         if (!jobs_dur)
-            hipLaunchKernelGGL(k_graph_decode, dim3(launch_grid_1d(g->n)), dim3(256), 0, st, out, g->n,
-                               (const GCtrl*)nullptr);
+            hipLaunchKernelGGL(k_graph_decode, dim3(launch_grid_1d(g->n)), dim3(256), 0, st, out, g->n);
         LLP_HIP(hipGetLastError());
         if (timing) LLP_HIP(hipEventRecord(ev1, st));
         s = readback(st, a.ctrl, &h, sizeof(h));
