@@ -449,18 +449,40 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
         const int Pk = shfl(R.pn, k - 1);
         const RowWin Rn = load_rows(a, v + k);
         // rows already at the bound are final (see dense_cap): their arcs are
-        // not read; an arc finds its row by binary search over the block's
-        // row starts in LDS (only when the block holds such a row)
+        // not read
         const uint64_t fin = cap < LLP_INF ? ballot(l < k && R.g >= cap) : 0ull;
         // weighted graphs: each row's arc bound (see dense_dmin), when any
         // row of the block has one
         const int thr = l < k ? arc_bound(R.g, dlo) : 0x7fffffff;
         const bool lim = ballot(thr != 0x7fffffff) != 0ull;
-        int* rs = cb + DBLK;
-        int* rt = rs + 64;
+        // the row of each arc position, when some row of the block is final
+        // or has a bound: row l writes l + 1 at its first position and a
+        // max-scan over the positions fills the rest (cb holds this table
+        // until the candidates are written); rt: per row, its arc bound or
+        // FINAL
+        constexpr int FINAL = (int)0x80000000;
+        int* rt = cb + DBLK;
         if (fin || lim) {
-            rs[l] = l < k ? R.pl - P0 : 0x7fffffff;
-            rt[l] = thr;
+            rt[l] = ((fin >> l) & 1ull) ? FINAL : thr;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) cb[8 * l + j] = 0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (l < k && R.pn > R.pl) cb[R.pl - P0] = l + 1;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            int q[8], run = 0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                run = max(run, cb[8 * l + j]);
+                q[j] = run;
+            }
+            int before = __shfl_up(wave_incl_max(run), 1, LLP_WAVE);
+            if (l == 0) before = 0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) cb[8 * l + j] = max(before, q[j]);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -476,13 +498,8 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
             act[j] = i < Pk;
             t[j] = 0x7fffffff;
             if ((fin || lim) && act[j]) {
-                const int p = l + 64 * j;
-                int o = 0;
-#pragma unroll
-                for (int step = 32; step >= 1; step >>= 1)
-                    if (o + step < k && rs[o + step] <= p) o += step;
-                act[j] = !((fin >> o) & 1ull);
-                t[j] = rt[o];
+                t[j] = rt[cb[l + 64 * j] - 1];
+                act[j] = t[j] != FINAL;
             }
             const int e = act[j] ? clampi(i, a.m, bad) : 0;
             u[j] = act[j] ? __builtin_nontemporal_load(a.in_src + e) : 0;
