@@ -119,10 +119,16 @@ __global__ void k_graph_init(GArgs a, const int* warm) {
         long long sum = 0;
         int cnt = 0;
         if (!a.unit_w && !a.jobs && a.in_w && a.m > 0) {
-            for (int i = threadIdx.x; i < 4096; i += blockDim.x) {
-                long long e = (long long)i * a.m / 4096;
-                sum += a.in_w[e];
+            // sample i of 4096 is arc i m / 4096; the 16 loads of a thread
+            // are issued before any is summed (the launch has 256 threads)
+            int wv[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int i = threadIdx.x + q * 256;
+                wv[q] = (threadIdx.x < 256) ? a.in_w[((long long)i * a.m) >> 12] : 0;
             }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) sum += wv[q];
             cnt = 4096;
         }
         sum = wave_sum64(sum);
