@@ -149,9 +149,11 @@ def fit(X, Y, steps, lr, seed, log):
 
 
 def training_graphs(quick=False):
-    """(name, EdgeList) of the training set: R-MAT scales 18-20 and 2048^2 grids."""
+    """(name, EdgeList) of the training set: R-MAT scales 18-22 and a 2048^2 grid
+    (seeds 100-107; the evaluation graphs use seed 900)."""
     out = []
-    scales = [(14, 100)] if quick else [(18, 100), (18, 101), (19, 102), (19, 103), (20, 104), (20, 105)]
+    scales = [(14, 100)] if quick else [(18, 100), (18, 101), (19, 102), (19, 103), (20, 104), (20, 105),
+                                        (21, 106), (22, 107)]
     for sc, seed in scales:
         out.append((f"rmat{sc}-s{seed}", llpgen.rmat_graph(sc, seed=seed), ("sssp", "bfs")))
     grids = [(64, 100)] if quick else [(2048, 106)]
@@ -171,18 +173,27 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--quick", action="store_true", help="tiny graphs (smoke test of the pipeline)")
+    ap.add_argument("--save-data", default="", help="also save the labelled rounds (.npz: X, Y)")
+    ap.add_argument("--load-data", default="", help="fit on labelled rounds saved earlier instead of labelling")
     a = ap.parse_args(argv)
 
     def log(msg):
         print(msg, flush=True)
 
     X, Y = [], []
-    for name, g, kinds in training_graphs(a.quick):
-        rows = a.grid_rows if name.startswith("grid") else a.rows
-        reps = a.reps
-        x, y = label_graph(name, g, kinds, rows, a.horizon, reps, log, seed=a.seed)
-        X += x
-        Y += y
+    if a.load_data:
+        d = np.load(a.load_data)
+        X, Y = list(d["X"]), [int(y) for y in d["Y"]]
+        log(f"loaded {len(Y)} labelled rounds from {a.load_data}")
+    else:
+        for name, g, kinds in training_graphs(a.quick):
+            rows = a.grid_rows if name.startswith("grid") else a.rows
+            reps = a.reps
+            x, y = label_graph(name, g, kinds, rows, a.horizon, reps, log, seed=a.seed)
+            X += x
+            Y += y
+    if a.save_data:
+        np.savez(a.save_data, X=np.asarray(X, np.float32), Y=np.asarray(Y, np.int32))
     p, acc = fit(X, Y, a.steps, a.lr, a.seed, log)
     np.save(a.out, p.astype(np.float32))
     with open(os.path.splitext(a.out)[0] + ".json", "w") as f:
