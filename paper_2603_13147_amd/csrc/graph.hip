@@ -206,7 +206,7 @@ struct GShared {
     int epre[MAX_SEG + 1];
     union {
         int own[GW][64];      // list iterator: owner slots
-        int dcb[GW][DBLK + 128];  // dense blocks: candidate of each arc, the rows' starts, their arc bounds
+        int dcb[GW][DBLK + 192];  // dense blocks: candidate (or row) of each position; per row: bound, first arc, first position
         int pw[GW][4][64];    // push blocks: entry start, source value, row base, duration
     };
     unsigned long long ctr;    // appends to the phase's main output list
@@ -437,7 +437,8 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
             continue;
         }
         first = false;
-        if (d0 > DBLK) {
+        // a row at the bound is final (see dense_cap): none of its arcs is read
+        if (d0 > DBLK && !(cap < LLP_INF && shfl(R.g, 0) >= cap)) {
             const RowWin Rn = load_rows(a, v + 1);
             const int hi = d0 <= DLONG ? P1 : min(we, P1);
             const int g0 = shfl(R.g, 0);
@@ -447,35 +448,45 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
             ++v;
             continue;
         }
-        // a block of rows v .. v+k-1 with at most DBLK arcs, all starting
-        // inside the range
-        const bool ok = v + l < a.n && R.pl < we && R.pn - P0 <= DBLK;
+        // a block of rows v .. v+k-1, all starting inside the range, whose
+        // arcs to read number at most DBLK: a final row has none, so the
+        // block's positions 0 .. C-1 run over the other rows' arcs in order
+        // (row l from position cs)
+        const bool finl = cap < LLP_INF && v + l < a.n && R.g >= cap;
+        const int len = (v + l < a.n && !finl) ? R.pn - R.pl : 0;
+        const int incl = cap < LLP_INF ? wave_incl_sum(len) : R.pn - P0;   // no final rows: arcs in order
+        const bool ok = v + l < a.n && R.pl < we && incl <= DBLK;
         const uint64_t stop = ~ballot(ok);
         const int k = stop ? __ffsll((long long)stop) - 1 : 64;   // >= 1: row v qualifies
-        const int Pk = shfl(R.pn, k - 1);
+        const int C = shfl(incl, k - 1);
+        const int cs = incl - len;
         const RowWin Rn = load_rows(a, v + k);
-        // rows already at the bound are final (see dense_cap): their arcs are
-        // not read
-        const uint64_t fin = cap < LLP_INF ? ballot(l < k && R.g >= cap) : 0ull;
+        const uint64_t fin = ballot(l < k && finl);
         // weighted graphs: each row's arc bound (see dense_dmin), when any
         // row of the block has one
         const int thr = l < k ? arc_bound(R.g, dlo) : 0x7fffffff;
         const bool lim = ballot(thr != 0x7fffffff) != 0ull;
         // the row of each arc position, when some row of the block is final
-        // or has a bound: row l writes l + 1 at its first position and a
-        // max-scan over the positions fills the rest (cb holds this table
-        // until the candidates are written); rt: per row, its arc bound or
-        // FINAL
-        constexpr int FINAL = (int)0x80000000;
+        // (positions skip its arcs) or has a bound: row l writes l + 1 at its
+        // first position and a max-scan over the positions fills the rest (cb
+        // holds this table until the candidates are written); per row: rt its
+        // arc bound, ra its first arc, rc its first position
         int* rt = cb + DBLK;
-        if (fin || lim) {
-            rt[l] = ((fin >> l) & 1ull) ? FINAL : thr;
+        int* ra = rt + 64;
+        int* rc = ra + 64;
+        const bool table = fin || lim;
+        if (table) {
+            rt[l] = thr;
+            if (fin) {
+                ra[l] = R.pl;
+                rc[l] = cs;
+            }
 #pragma unroll
             for (int j = 0; j < 8; ++j) cb[8 * l + j] = 0;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (l < k && R.pn > R.pl) cb[R.pl - P0] = l + 1;
+            if (l < k && len > 0) cb[cs] = l + 1;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -500,12 +511,14 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
         bool act[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const int i = P0 + l + 64 * j;
-            act[j] = i < Pk;
+            const int p = l + 64 * j;
+            act[j] = p < C;
             t[j] = 0x7fffffff;
-            if ((fin || lim) && act[j]) {
-                t[j] = rt[cb[l + 64 * j] - 1];
-                act[j] = t[j] != FINAL;
+            int i = P0 + p;
+            if (table && act[j]) {
+                const int o = cb[p] - 1;
+                t[j] = rt[o];
+                if (fin) i = ra[o] + (p - rc[o]);   // positions skip the final rows' arcs
             }
             const int e = act[j] ? clampi(i, a.m, bad) : 0;
             u[j] = act[j] ? __builtin_nontemporal_load(a.in_src + e) : 0;
@@ -524,12 +537,12 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
         arc_cands<8>(a, u, w, act, c, ovf);
 #pragma unroll
         for (int j = 0; j < 8; ++j) cb[l + 64 * j] = c[j];   // positions past the block are never read
-        if (bad) record_diag(a.ctrl->diag, 46, v, P0, Pk, a.n);
+        if (bad) record_diag(a.ctrl->diag, 46, v, P0, C, a.n);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         int x = 0;
-        const int lo = R.pl - P0, hi = R.pn - P0;   // rows of the block: within [0, DBLK]
+        const int lo = cs, hi = cs + len;   // positions of the row: within [0, DBLK]
         if (l < k && hi - lo <= DSHORT) {
             // four independent maxima: four LDS reads in flight
             int i = lo, x1 = 0, x2 = 0, x3 = 0;
