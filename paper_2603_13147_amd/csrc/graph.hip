@@ -207,7 +207,7 @@ struct GShared {
     union {
         int own[GW][64];      // list iterator: owner slots
         int dcb[GW][DBLK + 192];  // dense blocks: candidate (or row) of each position; per row: bound, first arc, first position
-        int pw[GW][4][64];    // push blocks: entry start, source value, row base, duration
+        int pw[GW][8][64];    // push blocks: entry start, source value, row base, duration; entry of each position
     };
     unsigned long long ctr;    // appends to the phase's main output list
     unsigned long long cctr;   // PRE in pull rounds: entries carried into CL[r]
@@ -697,14 +697,38 @@ __device__ void push_wave(const GArgs& a, const Src& src, int wb, int we, int r,
         if (put) lmin = min(lmin, LLP_INF - gu);
         const int kc = __popcll(ballot(put));
         if (l == 0 && kc && a.trace) atomicAdd(&sh.carried, kc);
-        pw[0][l] = valid ? e.z : LLP_INF;
         pw[1][l] = carry ? 0 : gu;
         pw[2][l] = e.y - e.z;
         pw[3][l] = du;
+        // entry of each of the block's positions: every entry starting in
+        // the block (entry 0 may start before it) writes l + 1 at its first
+        // position and a max-scan over the positions fills the rest
+        int* tab = &pw[4][0];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) tab[4 * l + j] = 0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // arcs: entry by binary search, then every load before any check
+        if (valid && e.z < limit) tab[e.z > base ? e.z - base : 0] = l + 1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        {
+            int q[4], run = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                run = max(run, tab[4 * l + j]);
+                q[j] = run;
+            }
+            int before = __shfl_up(wave_incl_max(run), 1, LLP_WAVE);
+            if (l == 0) before = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) tab[4 * l + j] = max(before, q[j]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // arcs: entry from the table, then every load before any check
         int x[PJ], c[PJ], g[PJ], d[PJ], w[PJ];
         bool bad = false;
 #pragma unroll
@@ -714,11 +738,7 @@ __device__ void push_wave(const GArgs& a, const Src& src, int wb, int we, int r,
             d[j] = 0;
             int ei = 0;
             if (p < limit) {
-                // last entry starting at or before p (entry 0 starts at or before base)
-                int o = 0;
-#pragma unroll
-                for (int step = 32; step >= 1; step >>= 1)
-                    if (o + step < nv && pw[0][o + step] <= p) o += step;
+                const int o = tab[l + 64 * j] - 1;   // last entry starting at or before p
                 g[j] = pw[1][o];
                 d[j] = pw[3][o];
                 ei = clampi(p + pw[2][o], a.m, bad);
