@@ -415,7 +415,7 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
                            bool& ovf, long long& nadv, int& lmin, int cap, int dlo, int& nrd, int& nins) {
     if (wb >= we) return;
     const int l = lane();
-    DenseSrc ds{a.in_ptr, a.n, a.ctrl->diag, 0};
+    DenseSrc ds{a.in_ptr, a.n, a.ctrl->diag};
     int v = ds.locate(wb).s;
     RowWin R = load_rows(a, v);
     bool first = true;

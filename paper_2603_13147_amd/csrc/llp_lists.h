@@ -106,7 +106,6 @@ struct DenseSrc {
     const int* ptr;
     int n;          // rows
     int* diag;
-    int vmod;       // > 0: row r is vertex r % vmod (slice-major blocked rows)
 
     // largest v with ptr[v] <= e (e < ptr[n]); 64-ary search, wave-uniform result
     __device__ Cursor locate(int e) const {
@@ -129,7 +128,7 @@ struct DenseSrc {
         int v = c.s + l;
         int vv = guard(v, n, diag, 14, c.s, l);
         int b = ptr[vv];
-        return make_int4(vmod > 0 ? v % vmod : v, b, b, ptr[vv + 1] - b);
+        return make_int4(v, b, b, ptr[vv + 1] - b);
     }
     __device__ Cursor advance(Cursor c, int k) const { c.s += k; return c; }
 };
