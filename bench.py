@@ -340,12 +340,17 @@ def main():
         dev = [torch.from_numpy(x).cuda() for x in (pp, pi, du, sp, si)]
         wsj = llp.workspace(llp.KIND_JOBS, 1 << 20, int(pi.shape[0]))
         jr = med_ms(lambda st: llp.jobs(*dev, ws=wsj, stats=st, flags=llp.TIMING))
-        jp = med_ms(lambda st: llp.jobs(*dev, ws=wsj, stats=st, flags=llp.TIMING, pull=True))
+        # the pull form is the generic sweep: timed with the headline's hybrid
+        # schedule and with the plain one
+        jp = med_ms(lambda st: llp.jobs(*dev, ws=wsj, stats=st, flags=llp.TIMING, pull=True,
+                                        sched=llp.SCHED_HYBRID))
+        jpp = med_ms(lambda st: llp.jobs(*dev, ws=wsj, stats=st, flags=llp.TIMING, pull=True))
         st = llp.Stats()
         llp.jobs(*dev, ws=wsj, stats=st)
         out["jobs"] = {"n": 1 << 20, "arcs": int(pi.shape[0]), "readiness_ms": round(jr, 3), "pull_ms": round(jp, 3),
-                       "levels": st.rounds}
-        print(f"# stable marriage {sm_ms:.3f} ms, jobs {jr:.3f} / {jp:.3f} ms", file=sys.stderr, flush=True)
+                       "pull_plain_ms": round(jpp, 3), "levels": st.rounds}
+        print(f"# stable marriage {sm_ms:.3f} ms, jobs {jr:.3f} / {jp:.3f} (plain {jpp:.3f}) ms", file=sys.stderr,
+              flush=True)
 
     if not a.no_cpu_baseline:
         import oracle
