@@ -105,7 +105,7 @@ typedef struct {
 /* One record per round when LLP_TRACE is set (device buffer of trace_cap records). */
 typedef struct {
     int32_t round;
-    int32_t mode;             /* bit 0 push, bit 1 dense, bits 8.. delta class */
+    int32_t mode;             /* round code (LLP_ROUND_CODE): bits 0-1 mode, bits 8-9 delta class */
     int32_t in_count;         /* changed indices the round consumed (its input list) */
     int32_t out_count;        /* pull rounds: candidates evaluated; 0 for dense and push rounds */
     int64_t in_edges;         /* out-arcs of the input list */
