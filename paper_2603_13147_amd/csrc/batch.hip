@@ -108,13 +108,16 @@ __device__ int knap_wg(const int* wt, const int* val, int items, int W, int* buf
 
 // --------------------------------------------------------------- small SSSP
 // Solve one SSSP instance (out-CSR) with the calling workgroup.  G: LDS
-// int[n]; cur, nxt: LDS bitmaps of ceil(n/32) words; fl: LDS int[4].
-// dist: output int[n].  Returns the status (uniform).
-__device__ int sssp_wg(const int* ptr, const int* dst, const int* wgt, int n, int m, int src, int* G,
-                       unsigned* cur, unsigned* nxt, int* fl, int* dist, int max_rounds, int* rounds_out) {
+// int[n]; cur, nxt: LDS bitmaps of ceil(n/32) words; ptr: LDS int[n + 1],
+// filled from gptr; fl: LDS int[4].  dist: output int[n].  Returns the
+// status (uniform).
+__device__ int sssp_wg(const int* gptr, const int* dst, const int* wgt, int n, int m, int src, int* G,
+                       unsigned* cur, unsigned* nxt, int* ptr, int* fl, int* dist, int max_rounds,
+                       int* rounds_out) {
     const int T = blockDim.x, t = threadIdx.x;
     const int words = (n + 31) >> 5;
     for (int v = t; v < n; v += T) G[v] = (v == src) ? LLP_INF : 0;
+    for (int v = t; v <= n; v += T) ptr[v] = gptr[v];   // row offsets held in LDS for every round
     for (int i = t; i < words; i += T) {
         cur[i] = (i == (src >> 5)) ? (1u << (src & 31)) : 0u;
         nxt[i] = 0u;
@@ -262,7 +265,9 @@ __device__ void batch_one(const BArgs& a, int i, int* lds, int* sfl) {
             int* G = lds;
             unsigned* cur = (unsigned*)(lds + a.ss_n);
             unsigned* nxt = cur + ((a.ss_n + 31) >> 5);
-            st = sssp_wg(ptr, dst, wgt, n, (int)m, src, G, cur, nxt, sfl, a.out_pool + d.out_off, n + 2, nullptr);
+            int* lptr = (int*)(nxt + ((a.ss_n + 31) >> 5));
+            st = sssp_wg(ptr, dst, wgt, n, (int)m, src, G, cur, nxt, lptr, sfl, a.out_pool + d.out_off, n + 2,
+                         nullptr);
             (void)words;
         }
     } else {
@@ -500,7 +505,8 @@ static int batch_plan(int32_t count, const llp_instance* desc, const llp_opts& o
     p->kn_w = h.max_w;
     p->ss_n = h.max_n > 0 ? h.max_n : 1;
     const size_t row = (size_t)(p->kn_w + 1) * 4;
-    const size_t ss = (size_t)p->ss_n * 4 + 2 * (size_t)((p->ss_n + 31) / 32) * 4;
+    // SSSP: state, two frontier bitmaps and the row offsets
+    const size_t ss = (size_t)p->ss_n * 4 + 2 * (size_t)((p->ss_n + 31) / 32) * 4 + (size_t)(p->ss_n + 1) * 4;
     size_t need1 = row > ss ? row : ss;
     size_t need2 = 2 * row > ss ? 2 * row : ss;
     p->kn_dbuf = need2 <= lds_limit();
