@@ -192,8 +192,9 @@ int llp_solve_bfs(const llp_graph* g, int32_t source, int32_t* level, const llp_
    range), LLP_E_INFEASIBLE (a man exhausts his list: malformed lists).
    With the default schedule, no warm start and no chunk, n <= 12288 runs in
    one workgroup with the matching state in LDS, from a per-solve table of
-   (woman, her rank of the man) by man and list position; the workspace then
-   holds n * n int32 for it (llp_workspace_bytes(LLP_KIND_SM, n, 0, opts)). */
+   (woman, her rank of the man) for the first 64 positions of every list
+   (later positions read both arrays); the workspace then holds 64 n int32
+   for it (llp_workspace_bytes(LLP_KIND_SM, n, 0, opts)). */
 int llp_solve_sm(int32_t n, const int16_t* men_pref, const int16_t* women_rank, int32_t* wife,
                  int32_t* proposal_idx, const llp_opts* opts);
 

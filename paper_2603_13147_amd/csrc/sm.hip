@@ -61,7 +61,7 @@ struct SArgs {
     int chunk;            // proposals per thread per launch, 0 = unbounded
     int random;           // random rounds
     unsigned long long seed;
-    int* combo;           // n <= SM_LDS_MAX: [n * n] w | rank of m for w << 16, by man and list position
+    int* combo;           // n <= SM_LDS_MAX: [n * SM_COMBO] w | rank of m for w << 16, by man and list position
 };
 
 __device__ __forceinline__ unsigned long long sm_key(int rank, int man, int idx) {
@@ -236,20 +236,28 @@ __global__ void k_sm_chain(SArgs a, int r) {
 // dependent; across XCDs an atomic must reach the memory side).  Thread t
 // starts men t, t + 1024, ... in turn and carries displaced men as above.
 constexpr int SM_LDS_MAX = 12288;   // 12 B of LDS per man: 144 KB
+constexpr int SM_COMBO = 64;        // list positions per man held as (woman, rank) pairs
 constexpr int SM_LDS_THREADS = 1024;
 
-// combo[m * n + i] = w | wrank[w][m] << 16 for the i-th woman w on m's list:
-// a chain step then reads one row (woman and her rank of m together)
-// instead of a list entry and then a rank.  Grid (ceil(n / 256), n).
+// The i-th woman w on m's list and her rank of m, as w | rank << 16.
+__device__ __forceinline__ int sm_pair(const SArgs& a, int m, int i) {
+    const int n = a.n;
+    const int w = guard(a.mpref[(long long)m * n + i], n, a.ctrl->diag, 4, m, i);
+    const int rk = guard(a.wrank[(long long)w * n + m], n, a.ctrl->diag, 5, w, m);
+    return w | (rk << 16);
+}
+
+// combo[m * SM_COMBO + i] = sm_pair(m, i) for the first SM_COMBO positions of
+// every list (men make about log n proposals on average): a chain step there
+// reads one entry (woman and her rank of m together) instead of a list entry
+// and then a rank; later positions read both.  One thread per entry.
 __global__ void k_sm_combo(SArgs a) {
     const int n = a.n;
-    const int m = blockIdx.y;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const long long x = (long long)m * n + i;
-    const int w = guard(a.mpref[x], n, a.ctrl->diag, 4, m, i);
-    const int rk = guard(a.wrank[(long long)w * n + m], n, a.ctrl->diag, 5, w, m);
-    a.combo[x] = w | (rk << 16);
+    const int k = min(n, SM_COMBO);
+    const long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (x >= (long long)n * k) return;
+    const int m = (int)(x / k), i = (int)(x % k);
+    a.combo[(long long)m * SM_COMBO + i] = sm_pair(a, m, i);
 }
 
 __global__ void __launch_bounds__(SM_LDS_THREADS) k_sm_lds(SArgs a) {
@@ -274,11 +282,17 @@ __global__ void __launch_bounds__(SM_LDS_THREADS) k_sm_lds(SArgs a) {
             const int la = min(SM_LOOKAHEAD, n - g);
             int wv[SM_LOOKAHEAD], cw[SM_LOOKAHEAD];
             unsigned long long kv[SM_LOOKAHEAD], bv[SM_LOOKAHEAD];
+            if (g + SM_LOOKAHEAD <= SM_COMBO) {   // the whole look-ahead window is in the table
 #pragma unroll
-            for (int i = 0; i < SM_LOOKAHEAD; ++i) cw[i] = i < la ? a.combo[(long long)m * n + g + i] : 0;
+                for (int i = 0; i < SM_LOOKAHEAD; ++i) cw[i] = i < la ? a.combo[(long long)m * SM_COMBO + g + i] : 0;
+            } else {
+#pragma unroll
+                for (int i = 0; i < SM_LOOKAHEAD; ++i)
+                    cw[i] = i >= la ? 0 : g + i < SM_COMBO ? a.combo[(long long)m * SM_COMBO + g + i] : sm_pair(a, m, g + i);
+            }
 #pragma unroll
             for (int i = 0; i < SM_LOOKAHEAD; ++i) {
-                wv[i] = cw[i] & 0xffff;   // < n: k_sm_combo guarded it
+                wv[i] = cw[i] & 0xffff;   // < n: sm_pair guarded it
                 kv[i] = ~0ull;
                 bv[i] = 0ull;
                 if (i < la) {
@@ -388,7 +402,7 @@ static size_t sm_ws(int64_t n, SArgs* a, char* base, size_t cap) {
     int* G = cv.take<int>(n);
     int* pend = cv.take<int>(n);
     SCtrl* ctrl = cv.take<SCtrl>(1);
-    int* combo = cv.take<int>(n <= SM_LDS_MAX ? n * n : 0);
+    int* combo = cv.take<int>(n <= SM_LDS_MAX ? (size_t)n * SM_COMBO : 0);
     if (a) {
         a->combo = combo;
         a->best = best;
@@ -457,7 +471,8 @@ int solve_sm(int32_t n, const int16_t* men_pref, const int16_t* women_rank, int3
     int status = LLP_OK;
     const bool lds = !rounds && a.chunk == 0 && !a.warm && n <= SM_LDS_MAX;
     if (lds) {
-        hipLaunchKernelGGL(k_sm_combo, dim3((n + 255) / 256, n), dim3(256), 0, st, a);
+        const long long entries = (long long)n * (n < SM_COMBO ? n : SM_COMBO);
+        hipLaunchKernelGGL(k_sm_combo, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, st, a);
         hipLaunchKernelGGL(k_sm_lds, dim3(1), dim3(SM_LDS_THREADS), 0, st, a);
         ++r;
     }
