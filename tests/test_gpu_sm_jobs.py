@@ -66,7 +66,8 @@ def test_sm_largest_lds_instance(kw):
 
 def test_sm_same_list_worst_case():
     # every man has the same list and every woman the same ranking: the
-    # proposal count is n (n + 1) / 2, the deepest displacement chains
+    # proposal count is n (n + 1) / 2, the deepest displacement chains; men
+    # reach list positions up to n - 1, past the 64 the (woman, rank) table holds
     n = 200
     mpref = np.tile(np.arange(n, dtype=np.int16), (n, 1))
     wrank = np.tile(np.arange(n, dtype=np.int16), (n, 1))
