@@ -244,10 +244,12 @@ def main():
                                f"+hamiltonian cycle, w U[1,255] / unit, source max-outdeg, seed 22",
                    "n": n, "m": m, "schedule": head + (f"+delta{a.delta}" if a.delta else "")},
         "sssp": {"gteps": round(m / (sssp_ms * 1e-3) / 1e9, 4), "ms": round(sssp_ms, 3),
-                 "rounds": s1.rounds, "edges_inspected": s1.edges_inspected, "push_edges": s1.push_edges,
+                 "rounds": s1.rounds, "edges_inspected": s1.edges_inspected,
+                 "states_gathered": s1.states_gathered, "push_edges": s1.push_edges,
                  "expand_edges": s1.expand_edges, "candidates": s1.candidates},
         "bfs": {"gteps": round(m / (bfs_ms * 1e-3) / 1e9, 4), "ms": round(bfs_ms, 3),
-                "rounds": s2.rounds, "edges_inspected": s2.edges_inspected, "push_edges": s2.push_edges,
+                "rounds": s2.rounds, "edges_inspected": s2.edges_inspected,
+                 "states_gathered": s2.states_gathered, "push_edges": s2.push_edges,
                 "expand_edges": s2.expand_edges, "candidates": s2.candidates},
         "roofline": {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
