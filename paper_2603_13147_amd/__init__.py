@@ -164,6 +164,32 @@ def _dev(t, dtype):
     return t.contiguous()
 
 
+def _out(t, shape, dtype, name):
+    """A caller-supplied output (or a new one when t is None): a contiguous GPU
+    tensor of exactly this dtype and shape, since the kernels write it whole."""
+    torch = _torch()
+    shape = tuple(int(x) for x in shape)
+    if t is None:
+        return torch.empty(shape, dtype=dtype, device="cuda")
+    _need(t, shape, dtype, name)
+    return t
+
+
+def _need(t, shape, dtype, name):
+    """Rejects anything but a contiguous GPU tensor of this dtype and shape."""
+    torch = _torch()
+    ok = (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()
+          and tuple(t.shape) == tuple(shape))
+    if not ok:
+        got = (f"{t.dtype} {tuple(t.shape)} on {t.device}" if isinstance(t, torch.Tensor) else type(t).__name__)
+        raise LLPError(E_ARG, f"{name} must be a contiguous {dtype} CUDA tensor of shape {tuple(shape)}, got {got}")
+
+
+def _length(t, k, name):
+    if t.dim() != 1 or int(t.shape[0]) != k:
+        raise LLPError(E_ARG, f"{name} must be one-dimensional with {k} entries, got shape {tuple(t.shape)}")
+
+
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
@@ -244,8 +270,7 @@ class DeviceGraph:
 
 def _graph_solve(fn, kind, dg, source, out, opts):
     torch = _torch()
-    if out is None:
-        out = torch.empty(dg.n, dtype=torch.int32, device="cuda")
+    out = _out(out, (dg.n,), torch.int32, "out")
     g = dg.cstruct()
     _check(fn(ctypes.byref(g), int(source), _ptr(out), ctypes.byref(opts)))
     return out
@@ -277,10 +302,8 @@ def stable_marriage(mpref, wrank, wife=None, prop=None, ws=None, **kw):
     n = int(mp.shape[0])
     if tuple(mp.shape) != (n, n) or tuple(wr.shape) != (n, n):
         raise LLPError(E_ARG, "mpref and wrank must both be n x n")
-    if wife is None:
-        wife = torch.empty(n, dtype=torch.int32, device="cuda")
-    if prop is None:
-        prop = torch.empty(n, dtype=torch.int32, device="cuda")
+    wife = _out(wife, (n,), torch.int32, "wife")
+    prop = _out(prop, (n,), torch.int32, "prop")
     if ws is None:
         ws = workspace(KIND_SM, n, 0)
     o = make_opts(workspace=ws, **kw)
@@ -296,8 +319,11 @@ def jobs(pred_ptr, pred_idx, dur, succ_ptr, succ_idx, out=None, ws=None, pull=Fa
     pp, pi, d = _dev(pred_ptr, torch.int32), _dev(pred_idx, torch.int32), _dev(dur, torch.int32)
     sp, si = _dev(succ_ptr, torch.int32), _dev(succ_idx, torch.int32)
     n = int(d.shape[0])
-    if out is None:
-        out = torch.empty(n, dtype=torch.int32, device="cuda")
+    _length(d, n, "dur")
+    _length(pp, n + 1, "pred_ptr")
+    _length(sp, n + 1, "succ_ptr")
+    _length(si, int(pi.shape[0]), "succ_idx (one entry per predecessor arc)")
+    out = _out(out, (n,), torch.int32, "out")
     if ws is None:
         ws = workspace(KIND_JOBS, n, int(pi.shape[0]))
     if pull:
@@ -315,6 +341,8 @@ def knapsack(wt, val, W, row=False, ws=None, **kw):
     torch = _torch()
     w_, v_ = _dev(wt, torch.int32), _dev(val, torch.int32)
     items = int(w_.shape[0])
+    _length(w_, items, "wt")
+    _length(v_, items, "val")
     best = torch.zeros(1, dtype=torch.int32, device="cuda")
     last = torch.empty(W + 1, dtype=torch.int32, device="cuda") if row else None
     if ws is None:
@@ -416,6 +444,8 @@ def transitive_closure(n, out_ptr, out_dst, ws=None, **kw):
     from u to v."""
     torch = _torch()
     p, d = _dev(out_ptr, torch.int32), _dev(out_dst, torch.int32)
+    _length(p, n + 1, "out_ptr")
+    _length(d, int(d.shape[0]), "out_dst")
     words = (n + 31) // 32
     bits = torch.empty((n, words), dtype=torch.int32, device="cuda")
     if ws is None:
@@ -430,6 +460,8 @@ def reduce_sum(x, ws=None, **kw):
     torch = _torch()
     if isinstance(x, np.ndarray):
         x = torch.from_numpy(np.ascontiguousarray(x, np.uint64).view(np.int64))
+    if x.dtype != torch.int64:
+        raise LLPError(E_ARG, f"x must hold 64-bit words (int64 tensor or uint64 array), got {x.dtype}")
     x = x.to(device="cuda").contiguous()
     out = torch.zeros(1, dtype=torch.int64, device="cuda")
     if ws is None:
@@ -457,6 +489,8 @@ def mlp_forward(params, x):
     """(logits[B,5] fp32, act[B,128] bf16 bits as int16) for device tensors params[5317], x[B,12]."""
     torch = _torch()
     B = int(x.shape[0])
+    _need(params, (MLP_PARAMS,), torch.float32, "params")
+    _need(x, (B, MLP_IN), torch.float32, "x")
     logits = torch.empty((B, MLP_OUT), dtype=torch.float32, device="cuda")
     act = torch.empty((B, 2 * MLP_HID), dtype=torch.int16, device="cuda")
     _check(lib().llp_mlp_forward(B, _ptr(params), _ptr(x), _ptr(logits), _ptr(act), _stream()))
@@ -467,6 +501,8 @@ def mlp_loss(logits, labels):
     """(loss[1] fp32, dlogits[B,5]) for round-code labels[B] int32."""
     torch = _torch()
     B = int(logits.shape[0])
+    _need(logits, (B, MLP_OUT), torch.float32, "logits")
+    _need(labels, (B,), torch.int32, "labels")
     dl = torch.empty_like(logits)
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
     _check(lib().llp_mlp_loss(B, _ptr(logits), _ptr(labels), _ptr(dl), _ptr(loss), _stream()))
@@ -475,13 +511,20 @@ def mlp_loss(logits, labels):
 
 def mlp_backward(params, x, act, dlogits, grad):
     """grad += d loss / d params (grad: fp32[5317] device tensor)."""
-    _torch()
+    torch = _torch()
     B = int(x.shape[0])
+    _need(params, (MLP_PARAMS,), torch.float32, "params")
+    _need(x, (B, MLP_IN), torch.float32, "x")
+    _need(act, (B, 2 * MLP_HID), torch.int16, "act")
+    _need(dlogits, (B, MLP_OUT), torch.float32, "dlogits")
+    _need(grad, (MLP_PARAMS,), torch.float32, "grad")
     _check(lib().llp_mlp_backward(B, _ptr(params), _ptr(x), _ptr(act), _ptr(dlogits), _ptr(grad), _stream()))
 
 
 def mlp_adam(grad, params, m1, m2, step, lr):
-    _torch()
+    torch = _torch()
+    for t, name in ((grad, "grad"), (params, "params"), (m1, "m1"), (m2, "m2")):
+        _need(t, (MLP_PARAMS,), torch.float32, name)
     _check(lib().llp_mlp_adam(_ptr(grad), _ptr(params), _ptr(m1), _ptr(m2), int(step), ctypes.c_float(lr),
                               _stream()))
 
@@ -489,6 +532,9 @@ def mlp_adam(grad, params, m1, m2, step, lr):
 def trace_features(trace, rounds, n, m):
     """features[rounds,12] fp32 (device) of a trace buffer filled by LLP_TRACE."""
     torch = _torch()
+    if not (isinstance(trace, torch.Tensor) and trace.is_cuda and trace.dtype == torch.uint8
+            and trace.is_contiguous() and trace.numel() >= rounds * ctypes.sizeof(TraceRec)):
+        raise LLPError(E_ARG, f"trace must be a contiguous uint8 CUDA buffer of at least {rounds} records")
     F = torch.empty((max(rounds, 1), MLP_IN), dtype=torch.float32, device="cuda")
     _check(lib().llp_trace_features(int(rounds), _ptr(trace), int(n), int(m), _ptr(F), _stream()))
     return F[:rounds]
