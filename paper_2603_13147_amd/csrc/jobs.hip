@@ -225,7 +225,9 @@ struct JobsLayout {
 
 static JobsLayout jobs_layout(int64_t n, int64_t E) {
     JobsLayout L;
-    L.nseg = device_info().cus;
+    // half a segment per CU: levels hold a few thousand jobs and every workgroup
+    // first scans all segment counts (at 2^20 jobs, 128 segments beat 256 by 2%; 64 lose 14%)
+    L.nseg = device_info().cus / 2;
     if (L.nseg > J_MAX_SEG) L.nseg = J_MAX_SEG;
     if (L.nseg < 1) L.nseg = 1;
     long long W = (long long)L.nseg * JW;
