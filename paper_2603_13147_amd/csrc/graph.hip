@@ -18,8 +18,8 @@
 // worklist WL (successor expansion, Section 4.2) or pushes along its
 // out-arcs.  MAIN evaluates the candidates (or every vertex in a dense round)
 // and produces CL[r].  A round whose input list is empty sets the device
-// `done` flag; later kernels return at once.  The host polls the flag every
-// few rounds.
+// `done` flag for the host and a stop word for the next launch; later
+// kernels return at once.  The host polls the flag every few rounds.
 #include <string.h>
 
 #include <algorithm>
@@ -51,6 +51,7 @@ struct GCtrl {
     int carried[2];     // entries carried by the delta filter, by round parity (traced solves)
     int step_phase[2];  // step kernel k: phase[k & 1] 0 = PRE of round step_round + 1, 1 = MAIN of step_round
     int step_round[2];
+    int stop[2];        // step launch k returns at once when stop[k & 1] is set (see k_graph_step)
     int diag[8];        // first guard event: site, index, bound, context
     long long rounds, cand, edges, adv, xedges, pedges, gath;
     SchedHist hist[2];  // scheduler history, double-buffered by round parity
@@ -873,6 +874,7 @@ __device__ int pre_phase(const GArgs& a, int r, int k, GShared& sh) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             a.ctrl->done = 1;
             a.ctrl->last_round = r - 1;
+            st_relaxed(&a.ctrl->stop[(k + 1) & 1], 1);
         }
         // the sweep has ended: every workgroup sees it, and no other launch
         // touches G any more, so the output is decoded here (unless a
@@ -891,6 +893,7 @@ __device__ int pre_phase(const GArgs& a, int r, int k, GShared& sh) {
             a.ctrl->over = 1;
             a.ctrl->done = 1;
             a.ctrl->last_round = r - 1;
+            st_relaxed(&a.ctrl->stop[(k + 1) & 1], 1);
         }
         return -1;
     }
@@ -1081,10 +1084,17 @@ __device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh
 // round is decided and evaluated in one launch (every workgroup takes the
 // same decision from the same list totals), so push and dense rounds cost
 // one launch, a pull round two.  The slots alternate, so no workgroup of
-// launch k reads the slot launch k writes.
+// launch k reads the slot launch k writes.  The same holds for the stop
+// word: the launch that finds the end (and decodes G, every workgroup its
+// share) sets stop[(k + 1) & 1] for the launches after it, each of which
+// passes it on; a workgroup of the finishing launch that starts late must
+// not see it, or its share of G would be left encoded.
 __global__ void __launch_bounds__(GB, 4) k_graph_step(GArgs a, int k) {
     __shared__ GShared sh;
-    if (ld_relaxed(&a.ctrl->done) || ld_relaxed(&a.ctrl->status)) return;
+    if (ld_relaxed(&a.ctrl->stop[k & 1]) || ld_relaxed(&a.ctrl->status)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st_relaxed(&a.ctrl->stop[(k + 1) & 1], 1);
+        return;
+    }
     const int ph = a.ctrl->step_phase[k & 1];
     const int rr = a.ctrl->step_round[k & 1];
     int r = rr, code;
