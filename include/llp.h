@@ -267,10 +267,16 @@ int llp_solve_batch(int32_t count, const llp_instance* desc, const int32_t* pool
                     int32_t* out_pool, int64_t out_words, int32_t* out_status, const llp_opts* opts);
 
 /* Batched solve replayed from an instantiated hipGraph cached by the library,
-   keyed by (desc, pool, out_pool, out_status, count, stream, block, chunk);
-   the first call measures, captures and instantiates, later calls only
-   launch the graph.  With LLP_ASYNC a replay returns once enqueued and the
-   batch status goes to opts->status_dev.  Same arguments and results as
+   keyed by (desc, pool, out_pool, out_status, workspace, count, pool and out
+   sizes, stream, block, chunk); the first call measures, captures and
+   instantiates, later calls only launch the graph.  Every replay measures
+   the instance limits and rebuilds the claim order inside the graph, so the
+   workspace may be used by other solves between replays and the table at
+   desc may change: when it then holds a larger knapsack W or SSSP n than
+   the captured launch was sized for, a synchronous call drops the graph,
+   captures a new one and solves again (with LLP_ASYNC those instances get
+   LLP_E_INPUT instead).  With LLP_ASYNC a replay returns once enqueued and
+   the batch status goes to opts->status_dev.  Same arguments and results as
    llp_solve_batch.  Released by llp_shutdown(). */
 int llp_solve_batch_graph(int32_t count, const llp_instance* desc, const int32_t* pool, int64_t pool_words,
                           int32_t* out_pool, int64_t out_words, int32_t* out_status, const llp_opts* opts);

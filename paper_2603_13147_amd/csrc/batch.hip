@@ -292,8 +292,59 @@ __global__ void __launch_bounds__(ch_max_block(CH)) k_batch(BArgs a) {
         __syncthreads();
         if (i0 >= a.count) break;
         const int i1 = min(i0 + a.chunk, a.count);
-        for (int i = i0; i < i1; ++i) batch_one<CH>(a, a.order[i], lds, sfl);
+        for (int i = i0; i < i1; ++i) {
+            const int j = a.order[i];   // uniform in the workgroup
+            if ((unsigned)j >= (unsigned)a.count) {
+                if (threadIdx.x == 0) set_status(&a.ctrl->status, LLP_E_HIP);
+                continue;
+            }
+            batch_one<CH>(a, j, lds, sfl);
+        }
     }
+}
+
+// Claim order, rebuilt on the device by every solve and every graph replay:
+// longest estimated cost first (longest-processing-time order), so the last
+// instances to start are the short ones.  Estimated cost: knapsack cells, or
+// 20 per SSSP arc (the ratio of the two measured per unit on this batch
+// kernel).  A one-workgroup counting sort over 256 cost classes (four per
+// octave), costliest class first; order within a class is arbitrary.
+constexpr int ORD_CLASSES = 256;
+
+__device__ __forceinline__ int cost_slot(const llp_instance& d) {
+    long long c = 0;
+    if (d.kind == LLP_KIND_KNAPSACK) c = (long long)max(d.n, 0) * (max(d.cap_or_source, 0) + 1);
+    else if (d.kind == LLP_KIND_SSSP) c = 20 * (d.m > 0 ? d.m : 0ll) + max(d.n, 0);
+    if (c <= 0) return ORD_CLASSES - 1;
+    const int e = 63 - __clzll((unsigned long long)c);
+    const int f = e >= 2 ? (int)((c >> (e - 2)) & 3) : (int)((c << (2 - e)) & 3);
+    return ORD_CLASSES - 1 - (4 * e + f);   // 4 e + f <= 251
+}
+
+__global__ void __launch_bounds__(1024) k_batch_order(const llp_instance* desc, int count, int* order) {
+    __shared__ int cnt[ORD_CLASSES];
+    const int t = threadIdx.x, T = blockDim.x;
+    for (int i = t; i < ORD_CLASSES; i += T) cnt[i] = 0;
+    __syncthreads();
+    for (int i = t; i < count; i += T) atomicAdd(&cnt[cost_slot(desc[i])], 1);
+    __syncthreads();
+    if (t < 64) {
+        // exclusive scan of the class counts, four classes per lane
+        int v[4], sum = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[j] = cnt[4 * t + j];
+            sum += v[j];
+        }
+        int run = wave_incl_sum(sum) - sum;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            cnt[4 * t + j] = run;
+            run += v[j];
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < count; i += T) order[atomicAdd(&cnt[cost_slot(desc[i])], 1)] = i;
 }
 
 // queue reset (a fill kernel, so the launch can be captured in a graph)
@@ -447,30 +498,6 @@ static int batch_ws(void** ws, const llp_opts& o, int64_t count) { return get_wo
 
 size_t batch_workspace_bytes(int64_t count) { return batch_bytes(count); }
 
-// Claim order: largest estimated cost first (longest-processing-time
-// order), so the last instances to start are the short ones.  Estimated
-// cost: knapsack cells, or 20 per SSSP arc (the ratio of the two measured per
-// unit on this batch kernel).  Written to order[count] on the device.
-static int batch_order(int32_t count, const llp_instance* desc, int* order, hipStream_t st) {
-    std::vector<llp_instance> h(count);
-    int s = readback(st, desc, h.data(), sizeof(llp_instance) * (size_t)count);
-    if (s) return s;
-    std::vector<std::pair<long long, int>> key(count);
-    for (int i = 0; i < count; ++i) {
-        const llp_instance& d = h[i];
-        long long c = 0;
-        if (d.kind == LLP_KIND_KNAPSACK) c = (long long)std::max(d.n, 0) * (std::max(d.cap_or_source, 0) + 1);
-        else if (d.kind == LLP_KIND_SSSP) c = 20 * std::max<long long>(d.m, 0) + d.n;
-        key[i] = {-c, i};
-    }
-    std::sort(key.begin(), key.end());
-    std::vector<int> ord(count);
-    for (int i = 0; i < count; ++i) ord[i] = key[i].second;
-    LLP_HIP(hipMemcpyAsync(order, ord.data(), sizeof(int) * (size_t)count, hipMemcpyHostToDevice, st));
-    LLP_HIP(hipStreamSynchronize(st));
-    return LLP_OK;
-}
-
 // Measure the limits over desc (one readback) and choose the launch shape.
 static int batch_plan(int32_t count, const llp_instance* desc, const llp_opts& o, BCtrl* ctrl, BatchPlan* p) {
     hipStream_t st = (hipStream_t)o.stream;
@@ -512,7 +539,7 @@ static int batch_plan(int32_t count, const llp_instance* desc, const llp_opts& o
     p->kn_dbuf = need2 <= lds_limit();
     p->lds = p->kn_dbuf ? need2 : need1;
     if (p->lds > lds_limit()) return fail(LLP_E_ARG, "instances need %zu bytes of LDS", p->lds);
-    return batch_order(count, desc, (int*)((char*)ctrl + 256), st);
+    return LLP_OK;
 }
 
 static int batch_grid(const BatchPlan& p, int count) {
@@ -547,6 +574,13 @@ static int batch_enqueue(const BatchPlan& p, int32_t count, const llp_instance* 
     a.kn_w = p.kn_w;
     a.kn_dbuf = p.kn_dbuf;
     a.ss_n = p.ss_n;
+    // limits and claim order are measured again by every launch sequence, so a
+    // captured graph stays valid whatever else uses the workspace between
+    // replays, and its replays see the current instance table
+    const int lg = std::min(std::max((count + 255) / 256, 1), 1024);
+    hipLaunchKernelGGL(k_batch_limits_reset, dim3(1), dim3(64), 0, st, ctrl);
+    hipLaunchKernelGGL(k_batch_limits, dim3(lg), dim3(256), 0, st, desc, count, ctrl);
+    hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, st, desc, count, (int*)a.order);
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, ctrl, (int*)nullptr);
     const int grid = batch_grid(p, count);
     int s = dispatch_ch(p.ch, [&](auto c) {
@@ -570,10 +604,12 @@ static int batch_args(int32_t count, const llp_instance* desc, const int32_t* po
     return LLP_OK;
 }
 
-static int batch_finish(hipStream_t st, BCtrl* ctrl) {
+static int batch_finish(hipStream_t st, BCtrl* ctrl, BCtrl* out = nullptr) {
     BCtrl h;
     int s = readback(st, ctrl, &h, sizeof(h));
     if (s) return s;
+    if (out) *out = h;
+    if (h.status == LLP_E_HIP) return fail(h.status, "claim order out of range");
     if (h.status == LLP_E_INPUT) return fail(h.status, "an instance is malformed or outside the pools");
     if (h.status == LLP_E_OVERFLOW) return fail(h.status, "an instance's result does not fit int32");
     if (h.status) return fail(h.status, "instance status %d", h.status);
@@ -643,11 +679,31 @@ struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int device = 0;
+    int kn_w = 0, ss_n = 0;   // largest knapsack W and SSSP n the captured launch holds
 };
 static std::map<GraphKey, GraphEntry> g_graphs;
 
+static int solve_batch_graph_once(int32_t count, const llp_instance* desc, const int32_t* pool, int64_t pool_words,
+                                  int32_t* out_pool, int64_t out_words, int32_t* out_status, const llp_opts* opts,
+                                  bool* outgrown);
+
+// A replay rebuilds the limits and the claim order inside the graph; when
+// the instance table at the same address now holds a larger knapsack W or
+// SSSP n than the captured launch's LDS plan, the replay marks those
+// instances LLP_E_INPUT and a synchronous call drops the graph, captures a
+// new one and solves again.
 int solve_batch_graph(int32_t count, const llp_instance* desc, const int32_t* pool, int64_t pool_words,
                       int32_t* out_pool, int64_t out_words, int32_t* out_status, const llp_opts* opts) {
+    bool outgrown = false;
+    int s = solve_batch_graph_once(count, desc, pool, pool_words, out_pool, out_words, out_status, opts, &outgrown);
+    if (outgrown) s = solve_batch_graph_once(count, desc, pool, pool_words, out_pool, out_words, out_status, opts,
+                                             nullptr);
+    return s;
+}
+
+static int solve_batch_graph_once(int32_t count, const llp_instance* desc, const int32_t* pool, int64_t pool_words,
+                                  int32_t* out_pool, int64_t out_words, int32_t* out_status, const llp_opts* opts,
+                                  bool* outgrown) {
     int s = batch_args(count, desc, pool, pool_words, out_pool, out_words);
     if (s || count == 0) return s;
     llp_opts o = opts_or_default(opts);
@@ -659,10 +715,15 @@ int solve_batch_graph(int32_t count, const llp_instance* desc, const int32_t* po
     int32_t* status_dev = (o.flags & LLP_ASYNC) ? o.status_dev : nullptr;
     GraphKey key{desc, pool, out_pool, out_status, o.stream, ws, count, o.block, o.chunk, pool_words, out_words};
     hipGraphExec_t exec = nullptr;
+    int plan_w = 0, plan_n = 0;
     {
         std::lock_guard<std::mutex> lk(g_bmu);
         auto it = g_graphs.find(key);
-        if (it != g_graphs.end()) exec = it->second.exec;
+        if (it != g_graphs.end()) {
+            exec = it->second.exec;
+            plan_w = it->second.kn_w;
+            plan_n = it->second.ss_n;
+        }
     }
     if (!exec) {
         BatchPlan p;
@@ -685,6 +746,8 @@ int solve_batch_graph(int32_t count, const llp_instance* desc, const int32_t* po
         ge.graph = graph;
         ge.exec = x;
         ge.device = device_info().device;
+        ge.kn_w = plan_w = p.kn_w;
+        ge.ss_n = plan_n = p.ss_n;
         g_graphs[key] = ge;
         exec = x;
     }
@@ -699,7 +762,18 @@ int solve_batch_graph(int32_t count, const llp_instance* desc, const int32_t* po
     if (status_dev) hipLaunchKernelGGL(k_batch_status, dim3(1), dim3(64), 0, st, ctrl, status_dev);
     if (timing) LLP_HIP(hipEventRecord(ev1, st));
     if (o.flags & LLP_ASYNC) return LLP_OK;
-    s = batch_finish(st, ctrl);
+    BCtrl h;
+    s = batch_finish(st, ctrl, &h);
+    if (outgrown && (h.bad_kind || h.max_w > plan_w || h.max_n > plan_n)) {
+        std::lock_guard<std::mutex> lk(g_bmu);
+        auto it = g_graphs.find(key);
+        if (it != g_graphs.end()) {
+            (void)hipGraphExecDestroy(it->second.exec);
+            (void)hipGraphDestroy(it->second.graph);
+            g_graphs.erase(it);
+        }
+        *outgrown = true;
+    }
     if (o.stats) {
         memset(o.stats, 0, sizeof(*o.stats));
         o.stats->candidates = count;

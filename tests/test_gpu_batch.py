@@ -168,3 +168,46 @@ def test_batch_full_size():
     b.solve(graph=True)
     torch.cuda.synchronize()
     check_batch(items, b)
+
+
+def test_batch_graph_replay_with_shared_workspace_and_grown_instance():
+    """Replays with the library-owned workspace (NULL in opts), which an SSSP
+    solve in between overwrites, still solve every instance; after the
+    instance table at the same address is edited to hold a larger knapsack
+    capacity than the captured launch was sized for, the next replay
+    captures again and the result matches the oracle."""
+    import ctypes
+    items = small_batch(seed=12, nk=24, ns=24)
+    b = llp.Batch(items)
+
+    def replay():
+        o = llp.make_opts()                      # workspace NULL: the library-owned buffer
+        llp._check(llp.lib().llp_solve_batch_graph(*b._args(), ctypes.byref(o)))
+        torch.cuda.synchronize()
+
+    replay()
+    check_batch(items, b)
+    g = llpgen.uniform_graph(4096, 32768, 1, 100, seed=1)
+    dg = llp.DeviceGraph(llpgen.CSRGraph(g, weighted=True, out_weights=True))
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    gs = dg.cstruct()
+    llp._check(llp.lib().llp_solve_sssp(ctypes.byref(gs), 0, llp._ptr(out), ctypes.byref(llp.make_opts())))
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), oracle.sssp(g.n, g.src, g.dst, g.w, 0))
+    b.out.fill_(-1)
+    b.status.fill_(-1)
+    replay()
+    check_batch(items, b)
+    # grow one knapsack instance's capacity in place (same arrays, same addresses)
+    desc = np.frombuffer(b.desc.cpu().numpy().tobytes(), llp.INSTANCE_DTYPE).copy()
+    k = int(np.nonzero(desc["kind"] == llp.KIND_KNAPSACK)[0][0])
+    newW = int(desc["cap_or_source"][desc["kind"] == llp.KIND_KNAPSACK].max()) + 3000
+    assert newW <= 16383
+    desc["cap_or_source"][k] = newW
+    b.desc.copy_(torch.from_numpy(desc.view(np.uint8).copy()))
+    _, wt, val, _ = items[k]
+    items[k] = ("knapsack", wt, val, newW)
+    b.out.fill_(-1)
+    b.status.fill_(-1)
+    replay()
+    check_batch(items, b)
