@@ -1,0 +1,123 @@
+"""Runs graph-sweep cases on the CPU emulation (tests/simt/_build/
+libllp_simt.so) and prints one JSON line per case: the status, the message
+and whether the output equals the oracle's.  Started by
+tests/test_simt_graph.py in a child process (so a fault or a sanitizer
+report ends only that process).  Usage: cases.py <case set>."""
+import ctypes
+import json
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+import llpgen  # noqa: E402
+import oracle  # noqa: E402
+import paper_2603_13147_amd as P  # noqa: E402
+
+L = ctypes.CDLL(os.path.join(HERE, "_build", "libllp_simt.so"))
+L.simt_alloc.restype = ctypes.c_void_p
+L.simt_alloc.argtypes = [ctypes.c_size_t]
+L.simt_free.argtypes = [ctypes.c_void_p]
+L.llp_last_error.restype = ctypes.c_char_p
+L.llp_workspace_bytes.restype = ctypes.c_size_t
+L.llp_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]
+for fn in (L.llp_solve_sssp, L.llp_solve_bfs):
+    fn.argtypes = [ctypes.POINTER(P.Graph), ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(P.Opts)]
+
+SCHEDS = [dict(sched=P.SCHED_PLAIN), dict(sched=P.SCHED_FIXED, flags=P.DENSE),
+          dict(sched=P.SCHED_FIXED, flags=P.PUSH), dict(sched=P.SCHED_HYBRID),
+          dict(sched=P.SCHED_RANDOM, seed=1), dict(sched=P.SCHED_RANDOM, seed=7),
+          dict(sched=P.SCHED_FIXED, delta=40), dict(sched=P.SCHED_FIXED, flags=P.PUSH, delta=7)]
+
+
+def dev(a):
+    """An emulated device copy of a; None (a null pointer, as torch gives) when empty."""
+    a = np.ascontiguousarray(a, np.int32)
+    if a.nbytes == 0:
+        return None
+    p = L.simt_alloc(a.nbytes)
+    ctypes.memmove(p, a.ctypes.data, a.nbytes)
+    return p
+
+
+def graph(e):
+    c = llpgen.CSRGraph(e, weighted=True, out_weights=True)
+    g = P.Graph()
+    g.n, g.m = c.n, c.m
+    g.in_ptr, g.in_src, g.in_w = dev(c.in_ptr), dev(c.in_src), dev(c.in_w)
+    g.out_ptr, g.out_dst, g.out_w = dev(c.out_ptr), dev(c.out_dst), dev(c.out_w)
+    return g
+
+
+def solve(kind, g, s, **kw):
+    """One solve with a fresh workspace of exactly llp_workspace_bytes, as the binding allocates."""
+    o = P.Opts()
+    o.size = ctypes.sizeof(P.Opts)
+    for k, v in kw.items():
+        setattr(o, k, v)
+    nb = max(int(L.llp_workspace_bytes(P.KIND_SSSP if kind == "sssp" else P.KIND_BFS, g.n, g.m, None)), 256)
+    o.workspace = L.simt_alloc(nb)
+    o.workspace_bytes = nb
+    outp = L.simt_alloc(4 * g.n)
+    fn = L.llp_solve_sssp if kind == "sssp" else L.llp_solve_bfs
+    st = fn(ctypes.byref(g), s, outp, ctypes.byref(o))
+    out = np.frombuffer((ctypes.c_char * (4 * g.n)).from_address(outp), np.int32).copy()
+    msg = L.llp_last_error().decode()
+    L.simt_free(o.workspace)
+    L.simt_free(outp)
+    return st, msg, out
+
+
+def report(name, e, s, kind, kw, want):
+    st, msg, got = solve(kind, graph(e), s, **kw)
+    print(json.dumps({"case": name, "kind": kind, "source": s, "opts": kw, "status": st, "msg": msg,
+                      "equal": bool(np.array_equal(got, want))}), flush=True)
+
+
+def edge_cases(sources=range(5), scheds=SCHEDS, isolated=True):
+    """n = 1 without arcs; a 5-vertex graph with self-loops, duplicate arcs,
+    zero weights, a vertex without out-arcs and an unreachable vertex, from
+    every source under every schedule; isolated vertices beside a chain."""
+    z = np.zeros(0, np.int32)
+    e1 = llpgen.EdgeList(1, z, z, z)
+    for kind in ("sssp", "bfs"):
+        report("n1", e1, 0, kind, {}, np.zeros(1, np.int32))
+    src = np.array([1, 1, 2, 2, 3, 0, 0], np.int32)
+    dst = np.array([1, 2, 3, 3, 3, 1, 1], np.int32)
+    w = np.array([0, 5, 1, 0, 4, 7, 2], np.int32)
+    e5 = llpgen.EdgeList(5, src, dst, w)
+    for s in sources:
+        ws, wb = oracle.sssp(5, src, dst, w, s), oracle.bfs(5, src, dst, s)
+        for kw in scheds:
+            report("five", e5, s, "sssp", kw, ws)
+            report("five", e5, s, "bfs", kw, wb)
+    if not isolated:
+        return
+    # vertices 0..2 a chain with zero weights, 3..7 isolated, 8 -> 9
+    src = np.array([0, 1, 8], np.int32)
+    dst = np.array([1, 2, 9], np.int32)
+    w = np.array([0, 0, 3], np.int32)
+    eiso = llpgen.EdgeList(10, src, dst, w)
+    for s in (0, 5, 8):
+        for kw in SCHEDS[:4]:
+            report("isolated", eiso, s, "sssp", kw, oracle.sssp(10, src, dst, w, s))
+            report("isolated", eiso, s, "bfs", kw, oracle.bfs(10, src, dst, s))
+
+
+def decode_race():
+    """4096 vertices (eight 512-vertex decode shares): the launch that finds
+    the end decodes G in every workgroup; run in index order, workgroup 0
+    first, every later workgroup of that launch must still decode its share."""
+    e = llpgen.uniform_graph(4096, 32768, 1, 100, seed=1)
+    want = oracle.sssp(e.n, e.src, e.dst, e.w, 0)
+    for kw in (dict(sched=P.SCHED_FIXED, flags=P.DENSE), dict(sched=P.SCHED_FIXED, flags=P.PUSH)):
+        report("decode", e, 0, "sssp", kw, want)
+
+
+if __name__ == "__main__":
+    {"edge": edge_cases,
+     "edge-wide": lambda: edge_cases(sources=(0, 2), scheds=SCHEDS[:4], isolated=False),
+     "decode": decode_race}[sys.argv[1]]()
