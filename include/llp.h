@@ -235,6 +235,18 @@ int llp_solve_tc(int32_t n, int64_t m, const int32_t* out_ptr, const int32_t* ou
    [device] modulo 2^64.  result [device, output] uint64[1]. */
 int llp_solve_reduce(int64_t n, const uint64_t* x, uint64_t* result, const llp_opts* opts);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+   capture, tight serving loops, harnesses that forbid allocation): the same
+   reduction as llp_solve_reduce with the same arguments and result, calling
+   no allocator.  Its scratch (a counter and one partial per tile, at most
+   2048 tiles: 16,640 bytes) is a static array that each GPU holds until the
+   process ends; opts->workspace is ignored.  Every call on a GPU uses that
+   GPU's one array, so calls that overlap on one GPU (other streams, other
+   threads) race and must be serialised by the caller.  LLP_E_ARG when the
+   launch would need more tiles than the array holds (only on a device of
+   more than 256 compute units) or with LLP_TIMING. */
+int llp_solve_reduce_noalloc(int64_t n, const uint64_t* x, uint64_t* result, const llp_opts* opts);
+
 /* Batched persistent solve: count independent instances in one launch of a
    persistent kernel; each workgroup takes `chunk` instances at a time from a
    device queue and solves each one on its own (workgroup-local sweep, state in

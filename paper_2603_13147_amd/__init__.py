@@ -119,6 +119,7 @@ def lib():
         ("llp_solve_knapsack", [i32, i32, vp, vp, vp, vp, po]),
         ("llp_solve_tc", [i32, i64, vp, vp, vp, po]),
         ("llp_solve_reduce", [i64, vp, vp, po]),
+        ("llp_solve_reduce_noalloc", [i64, vp, vp, po]),
         ("llp_solve_batch", [i32, vp, vp, i64, vp, i64, vp, po]),
         ("llp_solve_batch_graph", [i32, vp, vp, i64, vp, i64, vp, po]),
         ("llp_autotune_batch", [i32, vp, vp, i64, vp, i64, ctypes.c_char_p, sz, po]),
@@ -469,6 +470,18 @@ def reduce_sum(x, ws=None, **kw):
     o = make_opts(workspace=ws, **kw)
     _check(lib().llp_solve_reduce(x.numel(), _ptr(x), _ptr(out), ctypes.byref(o)))
     return int(out.cpu().numpy().view(np.uint64)[0])
+
+
+def reduce_sum_noalloc(x, out=None, **kw):
+    """reduce_sum through llp_solve_reduce_noalloc: no device allocation by the
+    library (x: an int64 CUDA tensor of the words' bits; out: optional int64[1]
+    CUDA tensor for the result)."""
+    torch = _torch()
+    _need(x, (x.numel(),), torch.int64, "x")
+    out = _out(out, (1,), torch.int64, "out")
+    o = make_opts(**kw)
+    _check(lib().llp_solve_reduce_noalloc(x.numel(), _ptr(x), _ptr(out), ctypes.byref(o)))
+    return out
 
 
 # ---------------------------------------------------------------- learned scheduler

@@ -17,6 +17,9 @@
 // counter observes, and it advances the root to the sum of the partials.
 #include <string.h>
 
+#include <map>
+#include <mutex>
+
 #include "llp_dev.h"
 #include "llp_host.h"
 
@@ -288,9 +291,70 @@ int solve_reduce(int64_t n, const uint64_t* x, uint64_t* result, const llp_opts*
     return LLP_OK;
 }
 
+// ---------------------------------------------------------------- no-allocation reduction
+// The same reduction with its scratch (the arrival counter and one partial
+// per tile) in a file-scope device array instead of a workspace: for callers
+// that cannot allocate.  Each GPU holds its own copy of the array; its
+// device address is looked up once per device (host code never passes the
+// array's name itself to a kernel).  Calls on one GPU share the array, so
+// calls that overlap on one GPU race; every call clears the counter first.
+constexpr int REDUCE_MAX_TILES = 2048;
+constexpr size_t REDUCE_SCRATCH_BYTES = 256 + (size_t)REDUCE_MAX_TILES * 8;
+static __device__ __align__(256) unsigned char scratch[REDUCE_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch;   // device -> device address of scratch
+
+static int scratch_ptr(void** out) {
+    int dev = 0;
+    LLP_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it == g_scratch.end()) {
+        void* p = nullptr;
+        LLP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(LLP_E_HIP, "no device address for the reduction scratch");
+        it = g_scratch.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return LLP_OK;
+}
+
+int solve_reduce_noalloc(int64_t n, const uint64_t* x, uint64_t* result, const llp_opts* opts) {
+    if (n < 0) return fail(LLP_E_ARG, "n must be >= 0");
+    if (!result || (n > 0 && !x)) return fail(LLP_E_ARG, "x and result are required");
+    llp_opts o = opts_or_default(opts);
+    if (o.flags & LLP_TIMING) return fail(LLP_E_ARG, "LLP_TIMING is not available without allocation");
+    hipStream_t st = (hipStream_t)o.stream;
+    const int grid = reduce_grid(n);
+    if (grid > REDUCE_MAX_TILES)
+        return fail(LLP_E_ARG, "%d tiles exceed the %d partials of the static scratch", grid, REDUCE_MAX_TILES);
+    void* sp = nullptr;
+    int s = scratch_ptr(&sp);
+    if (s) return s;
+    RCtrl* c = (RCtrl*)sp;
+    unsigned long long* partial = (unsigned long long*)((char*)sp + 256);
+    hipLaunchKernelGGL(k_reduce_reset, dim3(1), dim3(64), 0, st, c, (o.flags & LLP_ASYNC) ? o.status_dev : nullptr);
+    hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(RB), 0, st, (long long)n, (const unsigned long long*)x, partial,
+                       c, (unsigned long long*)result);
+    LLP_HIP(hipGetLastError());
+    if (o.flags & LLP_ASYNC) return LLP_OK;
+    LLP_HIP(hipStreamSynchronize(st));
+    if (o.stats) {
+        memset(o.stats, 0, sizeof(*o.stats));
+        o.stats->rounds = 2;
+        o.stats->advances = grid + 1;
+    }
+    return LLP_OK;
+}
+
 }  // namespace llp
 
 extern "C" {
+
+int llp_solve_reduce_noalloc(int64_t n, const uint64_t* x, uint64_t* result, const llp_opts* opts) {
+    return llp::solve_reduce_noalloc(n, x, result, opts);
+}
 
 int llp_solve_tc(int32_t n, int64_t m, const int32_t* out_ptr, const int32_t* out_dst, uint32_t* bits,
                  const llp_opts* opts) {
