@@ -19,11 +19,16 @@ The JSON line also carries
     schedules), plus the held-out evaluation graphs of the learned scheduler
     (R-MAT 22 seed 900, 4096^2 grid seed 900) when --heldout is given;
   - the batched persistent solve: 4096 knapsack + 4096 small SSSP instances
-    in one hipGraph-replayed launch (solves/s);
+    in one hipGraph-replayed launch (solves/s, median of 21 replays), the
+    same instances solved one by one through the single-instance entry
+    points (the batched-vs-plain speedup), per-kind rates and floors;
   - the roofline of the dominant kernel of the headline step (the kernel with
     the most device time: PRE = expansion / push, MAIN = pull evaluation),
     from HIP events around each of its launches on the solve's stream;
-  - the CPU oracle timed on the host on one SSSP solve of the same graph.
+  - the CPU oracle timed on the host on one full step of the same graph (an
+    SSSP and a BFS solve, adjacency lists built before the clock starts),
+    with binary-heap Dijkstra and queue BFS beside it, the host CPU model
+    and the CPUs visible.
 """
 from __future__ import annotations
 
@@ -66,6 +71,95 @@ def parse():
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only copy a 1 GiB device buffer 3 times (reference for rocprofv3 byte counters)")
     return p.parse_args()
+
+
+BATCH_REPLAYS = 21
+LDS_PEAK_BS = 128 * 256 * 2.4e9   # MI355X LDS: 128 B per clock per CU, 256 CUs, 2.4 GHz
+
+
+def host_cpu():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def batch_replay_ms(llp, b, torch):
+    """Median device time of BATCH_REPLAYS hipGraph replays (after the capture)."""
+    b.solve(graph=True)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(BATCH_REPLAYS):
+        st = llp.Stats()
+        b.solve(graph=True, stats=st, flags=llp.TIMING)
+        ts.append(st.device_ms)
+    return float(np.median(ts))
+
+
+def one_by_one(llp, items, b, res, torch):
+    """The batch's instances solved one at a time through the single-instance
+    entry points (llp_solve_knapsack, llp_solve_sssp: synchronous calls, inputs
+    already on the device, one workspace sized for the largest instance), with
+    the plain schedule and with the hybrid one; wall time of the whole loop and
+    equality of every output with the batch's."""
+    import ctypes
+    import llpgen
+    L = llp.lib()
+    prep = []
+    nmax = mmax = 1
+    for it in items:
+        if it[0] == "knapsack":
+            _, wt, val, W = it
+            prep.append(("k", llp._dev(wt, torch.int32), llp._dev(val, torch.int32), int(W)))
+        else:
+            _, g, s = it
+            dg = llp.DeviceGraph(llpgen.CSRGraph(g, weighted=True, out_weights=True))
+            prep.append(("s", dg, dg.cstruct(), int(s)))
+            nmax, mmax = max(nmax, g.n), max(mmax, int(g.m))
+    ws = llp.workspace(llp.KIND_SSSP, nmax, mmax)
+    best = torch.zeros(len(items), dtype=torch.int32, device="cuda")
+    dist = torch.zeros(max(int(b.out_words), 1), dtype=torch.int32, device="cuda")
+    got = {}
+    for name, sched in (("plain", llp.SCHED_PLAIN), ("hybrid", llp.SCHED_HYBRID)):
+        o = llp.make_opts(workspace=ws, sched=sched)
+        ok = llp.make_opts(workspace=ws)
+        ptrs = []
+        for i, p in enumerate(prep):
+            a, k = b.out_slices[i]
+            if p[0] == "k":
+                ptrs.append((0, p, best.data_ptr() + 4 * i))
+            else:
+                ptrs.append((1, p, dist.data_ptr() + 4 * a))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for kind, p, optr in ptrs:
+            if kind == 0:
+                st = L.llp_solve_knapsack(len(p[1]), p[3], llp._ptr(p[1]), llp._ptr(p[2]), ctypes.c_void_p(optr),
+                                          None, ctypes.byref(ok))
+            else:
+                st = L.llp_solve_sssp(ctypes.byref(p[2]), p[3], ctypes.c_void_p(optr), ctypes.byref(o))
+            if st:
+                raise llp.LLPError(st, L.llp_last_error().decode())
+        torch.cuda.synchronize()
+        got[name] = (time.perf_counter() - t0) * 1e3
+    # equality with the batch: knapsack bests and SSSP distances
+    r = res.cpu().numpy()
+    bb, dd = best.cpu().numpy(), dist.cpu().numpy()
+    equal = True
+    for i, p in enumerate(prep):
+        a, k = b.out_slices[i]
+        if p[0] == "k":
+            equal &= int(bb[i]) == int(r[a])
+        else:
+            equal &= bool(np.array_equal(dd[a:a + k], r[a:a + k]))
+    return {"plain_ms": round(got["plain"], 1), "hybrid_ms": round(got["hybrid"], 1),
+            "bit_exact_vs_batch": bool(equal),
+            "how": "each instance by its own synchronous llp_solve_knapsack / llp_solve_sssp call (inputs on the "
+                   "device, outputs written in place), wall time of the loop"}
 
 
 def sched_kw(llp, name, delta=0):
@@ -302,21 +396,36 @@ def main():
         items = llpgen.batch_workload(4096, 4096, seed=5)
         b = llp.Batch(items)
         tune = b.autotune()                      # launch shape (threads, instances per claim)
-        b.solve(graph=True)                      # measure, capture, instantiate with the tuned shape
-        torch.cuda.synchronize()
-        ts = []
-        for _ in range(5):
-            st = llp.Stats()
-            b.solve(graph=True, stats=st, flags=llp.TIMING)
-            ts.append(st.device_ms)
-        med = float(np.median(ts))
+        med = batch_replay_ms(llp, b, torch)
+        res = b.out.clone()
+        # the same instances one kind at a time (their own batches), for per-kind rates
+        kn = [it for it in items if it[0] == "knapsack"]
+        ss = [it for it in items if it[0] == "sssp"]
+        kn_ms = batch_replay_ms(llp, llp.Batch(kn), torch)
+        ss_ms = batch_replay_ms(llp, llp.Batch(ss), torch)
+        cells = sum(len(it[1]) * (it[3] + 1) for it in kn)
+        arcs = sum(int(it[1].m) for it in ss)
+        in_bytes = 4 * b.pool_words + b.desc.numel() + 4 * b.out_words
+        one = one_by_one(llp, items, b, res, torch)
         out["batch"] = {"workload": "4096 knapsack (items U[16,256], W U[256,4096]) + 4096 sssp "
                                     "(n U[256,4096], 8n arcs + cycle, w U[1,100]), seed 5, hipGraph replay",
-                        "instances": b.count, "ms": round(med, 3),
+                        "instances": b.count, "ms": round(med, 3), "replays": BATCH_REPLAYS,
                         "solves_per_s": round(b.count / (med * 1e-3), 1),
                         "tuned_shape": list(llp.autotune_get()),
-                        "untuned_ms": {f"{bl}x{ch}": ms for bl, ch, ms in tune}}
-        print(f"# batch: {med:.3f} ms", file=sys.stderr, flush=True)
+                        "untuned_ms": {f"{bl}x{ch}": ms for bl, ch, ms in tune},
+                        "knapsack_only_ms": round(kn_ms, 3), "sssp_only_ms": round(ss_ms, 3),
+                        "knapsack_cells": cells, "knapsack_gcells_per_s": round(cells / (kn_ms * 1e-3) / 1e9, 2),
+                        # a DP cell is one LDS row write and one shifted LDS read (8 B):
+                        # LDS peak 128 B per clock per CU x 256 CUs x 2.4 GHz
+                        "knapsack_lds_frac": round(8 * cells / (kn_ms * 1e-3) / LDS_PEAK_BS, 4),
+                        "sssp_arcs": arcs, "sssp_garcs_per_s": round(arcs / (ss_ms * 1e-3) / 1e9, 2),
+                        "hbm_floor_us": round(in_bytes / (HBM_PEAK_GBS * 1e9) * 1e6, 1),
+                        "hbm_floor_frac": round(in_bytes / (HBM_PEAK_GBS * 1e9) / (med * 1e-3), 4),
+                        "one_by_one": one,
+                        "speedup_batched_vs_plain": round(one["plain_ms"] / med, 1),
+                        "speedup_batched_vs_hybrid": round(one["hybrid_ms"] / med, 1)}
+        print(f"# batch: {med:.3f} ms; one by one: plain {one['plain_ms']:.1f} ms, hybrid {one['hybrid_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
 
     if not a.no_batch:
         # the other plugins at their full sizes (stable marriage n = 8192,
@@ -335,7 +444,8 @@ def main():
         st = llp.Stats()
         llp.stable_marriage(mpd, wrd, ws=wsm, stats=st)
         out["stable_marriage"] = {"n": 8192, "ms": round(sm_ms, 3), "solves_per_s": round(1e3 / sm_ms, 1),
-                                  "proposals": st.advances}
+                                  "proposals": st.advances,
+                                  "advances_per_s": round(st.advances / (sm_ms * 1e-3), 1)}
         del mpd, wrd
         pp, pi, du = llpgen.job_dag(1 << 20, seed=4)
         sp, si = llpgen.job_succ(pp, pi)
@@ -349,19 +459,34 @@ def main():
         jpp = med_ms(lambda st: llp.jobs(*dev, ws=wsj, stats=st, flags=llp.TIMING, pull=True))
         st = llp.Stats()
         llp.jobs(*dev, ws=wsj, stats=st)
+        # one bulk pass reads per arc the successor id, the parent's start and
+        # duration (12 B) and per job its two row offsets and start (12 B)
+        bulk = 12 * int(pi.shape[0]) + 12 * (1 << 20)
         out["jobs"] = {"n": 1 << 20, "arcs": int(pi.shape[0]), "readiness_ms": round(jr, 3), "pull_ms": round(jp, 3),
-                       "pull_plain_ms": round(jpp, 3), "levels": st.rounds}
+                       "pull_plain_ms": round(jpp, 3), "levels": st.rounds,
+                       "us_per_level": round(jr * 1e3 / max(st.rounds, 1), 2),
+                       "bulk_pass_floor_us": round(bulk / (HBM_PEAK_GBS * 1e9) * 1e6, 1),
+                       "bulk_pass_frac": round(bulk / (HBM_PEAK_GBS * 1e9) / (jr * 1e-3), 4)}
         print(f"# stable marriage {sm_ms:.3f} ms, jobs {jr:.3f} / {jp:.3f} (plain {jpp:.3f}) ms", file=sys.stderr,
               flush=True)
 
     if not a.no_cpu_baseline:
         import oracle
-        t3 = time.perf_counter()
-        oracle.sssp(n, g.src, g.dst, g.w, src, bag=True)
-        ct = time.perf_counter() - t3
-        out["cpu_baseline"] = {"value": round(m / ct / 1e9, 6), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-                               "sample": "one SSSP solve of the same graph by the single-threaded FIFO-bag "
-                                         f"oracle ({ct:.1f} s); BFS not timed"}
+        # one headline step (an SSSP and a BFS solve) by the single-threaded
+        # FIFO-bag oracle, adjacency lists built before its clock starts;
+        # binary-heap Dijkstra and queue BFS timed beside it for context
+        d_cpu, t_s = oracle.sssp_bag_timed(n, g.src, g.dst, g.w, src)
+        l_cpu, t_b = oracle.sssp_bag_timed(n, g.src, g.dst, None, src)
+        _, t_dj = oracle.dijkstra_timed(n, g.src, g.dst, g.w, src)
+        _, t_q = oracle.bfs_queue_timed(n, g.src, g.dst, src)
+        out["cpu_baseline"] = {"value": round(2 * m / (t_s + t_b) / 1e9, 6), "unit": "GTEPS", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"one full step of the same graph (FIFO-bag oracle SSSP {t_s:.1f} s + BFS "
+                                         f"{t_b:.1f} s, adjacency built beforehand, 1 thread)",
+                               "gpu_output_equal": bool(np.array_equal(d_cpu, dist.cpu().numpy())
+                                                        and np.array_equal(l_cpu, lev.cpu().numpy())),
+                               "dijkstra_s": round(t_dj, 3), "queue_bfs_s": round(t_q, 3),
+                               "host_cpu": host_cpu(), "host_cpus_visible": len(os.sched_getaffinity(0))}
     print(json.dumps(out), flush=True)
 
 

@@ -54,6 +54,10 @@ def _load():
     i32, i64 = ctypes.c_int32, ctypes.c_int64
     lib.oracle_sssp_cyclic.argtypes = [i32, i64, _i32p, _i32p, _i32p, i32, i64, _i32p, i32, _i32p, _i64p]
     lib.oracle_sssp_bag.argtypes = [i32, i64, _i32p, _i32p, _i32p, i32, _i32p, _i64p]
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_sssp_bag_timed.argtypes = [i32, i64, _i32p, _i32p, _i32p, i32, _i32p, _i64p, dp]
+    lib.oracle_dijkstra_timed.argtypes = [i32, i64, _i32p, _i32p, _i32p, i32, _i32p, dp]
+    lib.oracle_bfs_queue_timed.argtypes = [i32, i64, _i32p, _i32p, i32, _i32p, dp]
     lib.oracle_sm_scan.argtypes = [i32, _i16p, _i16p, i64, _i32p, _i32p, _i64p]
     lib.oracle_sm_bag.argtypes = [i32, _i16p, _i16p, _i32p, _i32p, _i64p]
     lib.oracle_jobs_cyclic.argtypes = [i32, _i32p, _i32p, _i32p, i64, _i32p, _i64p]
@@ -107,6 +111,38 @@ def sssp(n, src, dst, w, source, *, bag=False, max_passes=0, order=None, jacobi=
 
 def bfs(n, src, dst, source, **kw):
     return sssp(n, src, dst, None, source, **kw)
+
+
+def sssp_bag_timed(n, src, dst, w, source, check=True):
+    """(distances, seconds): the FIFO-bag oracle with the time of the solve
+    alone (its adjacency lists are built before the clock starts).  w=None
+    gives BFS levels."""
+    src, dst, w = _c32(src), _c32(dst), _c32(w)
+    out = np.empty(n, np.int32)
+    cnt, t = ctypes.c_int64(0), ctypes.c_double(0.0)
+    st = _load().oracle_sssp_bag_timed(n, src.shape[0], _p(src), _p(dst), _p(w), source, _p(out),
+                                       ctypes.byref(cnt), ctypes.byref(t))
+    return _ret(st, "sssp", out, check), t.value
+
+
+def dijkstra_timed(n, src, dst, w, source, check=True):
+    """(distances, seconds): binary-heap Dijkstra (a textbook cross-check, not
+    LLP); w=None gives unit weights."""
+    src, dst, w = _c32(src), _c32(dst), _c32(w)
+    out = np.empty(n, np.int32)
+    t = ctypes.c_double(0.0)
+    st = _load().oracle_dijkstra_timed(n, src.shape[0], _p(src), _p(dst), _p(w), source, _p(out),
+                                       ctypes.byref(t))
+    return _ret(st, "dijkstra", out, check), t.value
+
+
+def bfs_queue_timed(n, src, dst, source, check=True):
+    """(levels, seconds): FIFO-queue BFS (a textbook cross-check, not LLP)."""
+    src, dst = _c32(src), _c32(dst)
+    out = np.empty(n, np.int32)
+    t = ctypes.c_double(0.0)
+    st = _load().oracle_bfs_queue_timed(n, src.shape[0], _p(src), _p(dst), source, _p(out), ctypes.byref(t))
+    return _ret(st, "bfs", out, check), t.value
 
 
 # ------------------------------------------------------------------ stable marriage

@@ -26,9 +26,11 @@
  *
  * Build: gcc -O2 -shared -fPIC oracle.c -o liboracle.so   (single-threaded)
  */
+#define _POSIX_C_SOURCE 199309L
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 #define OR_OK 0
 #define OR_E_ARG 1
@@ -149,9 +151,40 @@ int oracle_sssp_cyclic(int32_t n, int64_t m, const int32_t* src, const int32_t* 
 /* Bag solver (FIFO bag with membership flags).  The bag starts with the
    source's out-neighbours; an advance of v pushes v's out-neighbours, the
    indices whose predicate reads d(v) (Section 4.2, problem-specific state
-   selection). */
-int oracle_sssp_bag(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
-                    const int32_t* w, int32_t source, int32_t* dist_out, int64_t* evals_out) {
+   selection).  sssp_bag_run works on adjacency lists built beforehand. */
+static void sssp_bag_run(int32_t n, const adj_t* in, const adj_t* out, const int32_t* src,
+                         const int32_t* dst, const int32_t* w, int32_t source, int64_t* d,
+                         int32_t* q, uint8_t* inq, int64_t* evals_out) {
+    for (int64_t v = 0; v < n; ++v) { d[v] = INF64; inq[v] = 0; }
+    d[source] = 0;
+    int64_t head = 0, size = 0, evals = 0;
+#define PUSH_OUT(u)                                                        \
+    for (int64_t k = out->rows[u]; k < out->rows[(u) + 1]; ++k) {          \
+        int32_t x = dst[out->arc[k]];                                      \
+        if (!inq[x] && x != source) { inq[x] = 1; q[(head + size) % n] = x; ++size; } \
+    }
+    PUSH_OUT(source);
+    while (size > 0) {
+        int32_t v = q[head]; head = (head + 1) % n; --size; inq[v] = 0;
+        ++evals;
+        int64_t a = sssp_alpha(in, src, w, d, v);
+        if (a < d[v]) { d[v] = a; PUSH_OUT(v); }
+    }
+#undef PUSH_OUT
+    *evals_out = evals;
+}
+
+static double now_s(void) {
+    struct timespec t;
+    clock_gettime(CLOCK_MONOTONIC, &t);
+    return (double)t.tv_sec + 1e-9 * (double)t.tv_nsec;
+}
+
+/* solve_s (nullable) receives the time of the solve alone: the adjacency
+   lists are built before the clock starts. */
+int oracle_sssp_bag_timed(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                          const int32_t* w, int32_t source, int32_t* dist_out, int64_t* evals_out,
+                          double* solve_s) {
     if (n <= 0 || m < 0 || source < 0 || source >= n) return OR_E_ARG;
     int st = check_graph(n, m, src, dst, w);
     if (st) return st;
@@ -159,26 +192,97 @@ int oracle_sssp_bag(int32_t n, int64_t m, const int32_t* src, const int32_t* dst
     if (adj_build(n, m, dst, &in) || adj_build(n, m, src, &out)) return OR_E_ARG;
     int64_t* d = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
     int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
-    uint8_t* inq = (uint8_t*)calloc((size_t)n, 1);
-    for (int64_t v = 0; v < n; ++v) d[v] = INF64;
-    d[source] = 0;
-    int64_t head = 0, size = 0, evals = 0;
-#define PUSH_OUT(u)                                                        \
-    for (int64_t k = out.rows[u]; k < out.rows[(u) + 1]; ++k) {            \
-        int32_t x = dst[out.arc[k]];                                       \
-        if (!inq[x] && x != source) { inq[x] = 1; q[(head + size) % n] = x; ++size; } \
-    }
-    PUSH_OUT(source);
-    while (size > 0) {
-        int32_t v = q[head]; head = (head + 1) % n; --size; inq[v] = 0;
-        ++evals;
-        int64_t a = sssp_alpha(&in, src, w, d, v);
-        if (a < d[v]) { d[v] = a; PUSH_OUT(v); }
-    }
-#undef PUSH_OUT
+    uint8_t* inq = (uint8_t*)malloc((size_t)n);
+    int64_t evals = 0;
+    double t0 = now_s();
+    sssp_bag_run(n, &in, &out, src, dst, w, source, d, q, inq, &evals);
+    if (solve_s) *solve_s = now_s() - t0;
     int status = sssp_output(n, d, dist_out);
     if (evals_out) *evals_out = evals;
     free(d); free(q); free(inq); adj_free(&in); adj_free(&out);
+    return status;
+}
+
+int oracle_sssp_bag(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                    const int32_t* w, int32_t source, int32_t* dist_out, int64_t* evals_out) {
+    return oracle_sssp_bag_timed(n, m, src, dst, w, source, dist_out, evals_out, NULL);
+}
+
+/* Cross-checks timed beside the oracle (textbook algorithms, not LLP):
+   Dijkstra with a binary heap of (distance, vertex) entries and lazy
+   deletion, and a FIFO-queue BFS, each over out-adjacency lists built
+   before the clock starts.  w == NULL: unit weights. */
+int oracle_dijkstra_timed(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                          const int32_t* w, int32_t source, int32_t* dist_out, double* solve_s) {
+    if (n <= 0 || m < 0 || source < 0 || source >= n) return OR_E_ARG;
+    int st = check_graph(n, m, src, dst, w);
+    if (st) return st;
+    adj_t out;
+    if (adj_build(n, m, src, &out)) return OR_E_ARG;
+    int64_t* d = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t cap = m + 1, size = 0;
+    int64_t* hk = (int64_t*)malloc(sizeof(int64_t) * (size_t)cap);
+    int32_t* hv = (int32_t*)malloc(sizeof(int32_t) * (size_t)cap);
+    double t0 = now_s();
+    for (int64_t v = 0; v < n; ++v) d[v] = INF64;
+    d[source] = 0;
+    hk[0] = 0; hv[0] = source; size = 1;
+    while (size > 0) {
+        int64_t k = hk[0];
+        int32_t u = hv[0];
+        --size;                                  /* pop: move the last entry down from the root */
+        int64_t i = 0;
+        while (size > 0) {
+            int64_t c = 2 * i + 1;
+            if (c >= size) break;
+            if (c + 1 < size && hk[c + 1] < hk[c]) ++c;
+            if (hk[c] >= hk[size]) break;
+            hk[i] = hk[c]; hv[i] = hv[c]; i = c;
+        }
+        if (size > 0) { hk[i] = hk[size]; hv[i] = hv[size]; }
+        if (k > d[u]) continue;                  /* stale entry */
+        for (int64_t a = out.rows[u]; a < out.rows[u + 1]; ++a) {
+            int64_t e = out.arc[a];
+            int64_t nd = k + (w ? w[e] : 1);
+            int32_t x = dst[e];
+            if (nd < d[x]) {
+                d[x] = nd;
+                int64_t j = size++;              /* push: sift up */
+                while (j > 0 && hk[(j - 1) / 2] > nd) { hk[j] = hk[(j - 1) / 2]; hv[j] = hv[(j - 1) / 2]; j = (j - 1) / 2; }
+                hk[j] = nd; hv[j] = x;
+            }
+        }
+    }
+    if (solve_s) *solve_s = now_s() - t0;
+    int status = sssp_output(n, d, dist_out);
+    free(d); free(hk); free(hv); adj_free(&out);
+    return status;
+}
+
+int oracle_bfs_queue_timed(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                           int32_t source, int32_t* level_out, double* solve_s) {
+    if (n <= 0 || m < 0 || source < 0 || source >= n) return OR_E_ARG;
+    int st = check_graph(n, m, src, dst, NULL);
+    if (st) return st;
+    adj_t out;
+    if (adj_build(n, m, src, &out)) return OR_E_ARG;
+    int64_t* d = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    double t0 = now_s();
+    for (int64_t v = 0; v < n; ++v) d[v] = INF64;
+    d[source] = 0;
+    int64_t head = 0, tail = 0;
+    q[tail++] = source;
+    while (head < tail) {
+        int32_t u = q[head++];
+        for (int64_t a = out.rows[u]; a < out.rows[u + 1]; ++a) {
+            int32_t x = dst[out.arc[a]];
+            if (d[x] == INF64) { d[x] = d[u] + 1; q[tail++] = x; }
+        }
+    }
+    if (solve_s) *solve_s = now_s() - t0;
+    int status = sssp_output(n, d, level_out);
+    free(d); free(q); adj_free(&out);
     return status;
 }
 
