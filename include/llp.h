@@ -54,10 +54,12 @@ typedef enum {
 /* Schedules.  Every schedule reaches the same least fixpoint. */
 #define LLP_SCHED_PLAIN   0u  /* pull over the in-CSR on a compacted candidate worklist */
 #define LLP_SCHED_FIXED   1u  /* the mode given by flags (LLP_PUSH / LLP_DENSE) and delta, every round */
-#define LLP_SCHED_LEARNED 2u  /* per round, the loaded MLP picks push/pull, dense/worklist and delta */
+#define LLP_SCHED_LEARNED 2u  /* per round, the loaded MLP picks push/pull, dense/worklist and delta; rounds
+                                 of fewer than m/256 frontier arcs take the HYBRID code instead */
 #define LLP_SCHED_HYBRID  3u  /* per round, a frontier-width threshold: dense when the changed vertices'
                                  out-arcs exceed a fraction of all arcs (SSSP 1/3, BFS 1/14, jobs 1/2),
-                                 push otherwise (pull without out_w) */
+                                 push otherwise (pull without out_w); on weighted graphs of 2 to 8
+                                 arcs per vertex the push rounds use the wide delta buckets */
 #define LLP_SCHED_RANDOM  4u  /* per round, a seeded random mode and delta class (schedule-independence tests) */
 #define LLP_SCHED_SCRIPT  5u  /* per round, the code opts->plan[r-1] (plain after the plan ends); used to
                                  measure what a decision at a given round costs when training the scheduler */
@@ -65,8 +67,9 @@ typedef enum {
 /* Round codes (llp_trace_rec.mode, opts->plan): bits 0-1 the mode (0 pull over
    the candidate worklist, 1 dense pull, 2 push), bits 8-9 the delta class:
    0 = the base width (2^floor(log2 of the mean arc weight), estimated from a
-   sample of the arcs; 1 for BFS), 1 = 8 x the base width, 2 = no buckets,
-   3 = opts->delta.  With a delta width D, a round only expands (or pushes
+   sample of the arcs; 1 for BFS), 1 = 64 x the base width, 2 = no buckets,
+   3 = opts->delta.  In LLP_SCHED_SCRIPT plans, mode 3 means "the round the
+   frontier-width hybrid would run".  With a delta width D, a round only expands (or pushes
    from) the changed vertices whose distance lies below floor(dmin / D) * D + D,
    dmin the smallest distance among them; the others are carried to the next
    round (delta-stepping buckets, paper Section 4.2).  Dense rounds ignore
@@ -339,8 +342,15 @@ int llp_mlp_adam(const float* grad, float* params, float* m1, float* m2, int32_t
                  void* stream);
 
 /* Per-round feature vector the sweep feeds the network (for trace-driven
-   training): 12 fp32 values per llp_trace_rec, see the implementation notes. */
-int llp_trace_features(int64_t rounds, const llp_trace_rec* trace, int32_t n, int64_t m,
+   training): 12 fp32 values per llp_trace_rec of a solve of the given kind
+   (LLP_KIND_SSSP, LLP_KIND_BFS or LLP_KIND_JOBS, with push rounds
+   available) on n indices and m arcs.  Features: frontier size and arcs
+   (log and linear, relative to n and m), the frontier's mean degree
+   relative to the graph's, the frontier-width hybrid's code for the round
+   (0 push, 0.5 push with wide buckets, 0.25 pull, 1 dense), log2(1 + m/n)/8,
+   the change of the frontier size, the previous round's mode, r/(r + 16),
+   and the changed indices so far over n; each rounded to bf16. */
+int llp_trace_features(int64_t rounds, const llp_trace_rec* trace, int32_t n, int64_t m, int32_t kind,
                        float* features /* [device, output] [rounds][12] */, void* stream);
 
 const char* llp_last_error(void);

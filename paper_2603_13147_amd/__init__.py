@@ -128,7 +128,7 @@ def lib():
         ("llp_mlp_loss", [i32, vp, vp, vp, vp, vp]),
         ("llp_mlp_backward", [i32, vp, vp, vp, vp, vp, vp]),
         ("llp_mlp_adam", [vp, vp, vp, vp, i32, ctypes.c_float, vp]),
-        ("llp_trace_features", [i64, vp, i32, i64, vp, vp]),
+        ("llp_trace_features", [i64, vp, i32, i64, i32, vp, vp]),
     ]:
         if hasattr(L, name):
             getattr(L, name).argtypes = args
@@ -542,14 +542,15 @@ def mlp_adam(grad, params, m1, m2, step, lr):
                               _stream()))
 
 
-def trace_features(trace, rounds, n, m):
-    """features[rounds,12] fp32 (device) of a trace buffer filled by LLP_TRACE."""
+def trace_features(trace, rounds, n, m, kind=KIND_SSSP):
+    """features[rounds,12] fp32 (device) of a trace buffer filled by LLP_TRACE
+    in a solve of the given kind (KIND_SSSP, KIND_BFS or KIND_JOBS)."""
     torch = _torch()
     if not (isinstance(trace, torch.Tensor) and trace.is_cuda and trace.dtype == torch.uint8
             and trace.is_contiguous() and trace.numel() >= rounds * ctypes.sizeof(TraceRec)):
         raise LLPError(E_ARG, f"trace must be a contiguous uint8 CUDA buffer of at least {rounds} records")
     F = torch.empty((max(rounds, 1), MLP_IN), dtype=torch.float32, device="cuda")
-    _check(lib().llp_trace_features(int(rounds), _ptr(trace), int(n), int(m), _ptr(F), _stream()))
+    _check(lib().llp_trace_features(int(rounds), _ptr(trace), int(n), int(m), int(kind), _ptr(F), _stream()))
     return F[:rounds]
 
 

@@ -589,19 +589,21 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
 constexpr int PJ = 4;
 constexpr int PBLK = 64 * PJ;
 
-// In-round continuation (push rounds without buckets): a lane that advanced
-// a target with at most CDEG out-arcs pushes that target's arcs right away
-// with its new value, up to CDEPTH steps deep, instead of leaving it to the
-// next round; targets it does not continue through are stamped and appended
-// as usual.  A continued vertex is not stamped, so if it advances again
-// later in the round its advancer appends it.  Chains (vertices of one or
-// two out-arcs) are what it shortens; through wider fan-out (a weighted
-// mesh) it spreads values that later rounds must correct, so it stops there.
+// In-round continuation (push rounds): a lane that advanced a target with at
+// most CDEG out-arcs pushes that target's arcs right away with its new
+// value, up to CDEPTH steps deep, instead of leaving it to the next round;
+// targets it does not continue through are stamped and appended as usual.
+// A continued vertex is not stamped, so if it advances again later in the
+// round its advancer appends it.  Chains (vertices of one or two out-arcs)
+// are what it shortens; through wider fan-out (a weighted mesh) it spreads
+// values that later rounds must correct, so it stops there.  In a round with
+// delta buckets it continues only through targets whose new distance lies
+// below the bucket's ceiling, as the round would have pushed them.
 constexpr int CDEG = 2;
 constexpr int CDEPTH = 32;
 constexpr int CONT_EDGES = 1 << 20;   // rounds with at most this many arcs to push
 
-__device__ void push_continue(const GArgs& a, int r, int cv, int cg, int cob, int cod, const ListRef& out,
+__device__ void push_continue(const GArgs& a, int r, int cv, int cg, int cob, int cod, long long hi, const ListRef& out,
                               unsigned long long* ctr, bool& ovf, long long& nadv, int& lmin) {
     for (int d = 0; d < CDEPTH; ++d) {
         if (!__any(cv >= 0)) return;
@@ -632,7 +634,8 @@ __device__ void push_continue(const GArgs& a, int r, int cv, int cg, int cob, in
                 yob = a.out_ptr[y[k]];
                 yod = a.out_ptr[y[k] + 1] - yob;
                 lmin = min(lmin, dist_key(a, cand[k]));
-                if (nv < 0 && yod > 0 && yod <= CDEG && d + 1 < CDEPTH) {
+                if (nv < 0 && yod > 0 && yod <= CDEG && d + 1 < CDEPTH &&
+                    (hi <= 0 || (long long)(LLP_INF - cand[k]) < hi)) {
                     nv = y[k];
                     ng = cand[k];
                     nob = yob;
@@ -657,7 +660,7 @@ __device__ void push_wave(const GArgs& a, const Src& src, int wb, int we, int r,
                           int& lmin) {
     if (wb >= we) return;
     const int l = lane();
-    const bool cont = hi <= 0 && !a.jobs && src.sv.total_edges <= CONT_EDGES;
+    const bool cont = !a.jobs && src.sv.total_edges <= CONT_EDGES;
     Cursor cur = src.locate(wb);
     int base = wb;
     int av = src.avail(cur);
@@ -771,7 +774,7 @@ __device__ void push_wave(const GArgs& a, const Src& src, int wb, int we, int r,
                     ob = a.out_ptr[x[j]];
                     od = a.out_ptr[x[j] + 1] - ob;
                     lmin = min(lmin, dist_key(a, c[j]));
-                    if (cont && cv < 0 && od > 0 && od <= CDEG) {
+                    if (cont && cv < 0 && od > 0 && od <= CDEG && (hi <= 0 || (long long)(LLP_INF - c[j]) < hi)) {
                         cv = x[j];
                         cg = c[j];
                         cob = ob;
@@ -784,7 +787,7 @@ __device__ void push_wave(const GArgs& a, const Src& src, int wb, int we, int r,
             if (changed) nadv++;
             append(changed && od > 0, x[j], ob, od, ctr, out, &a.ctrl->status);
         }
-        if (cont) push_continue(a, r, cv, cg, cob, cod, out, ctr, ovf, nadv, lmin);
+        if (cont) push_continue(a, r, cv, cg, cob, cod, hi, out, ctr, ovf, nadv, lmin);
         cur = nxt;
         base = limit;
         av = nav;
@@ -850,7 +853,7 @@ __device__ __forceinline__ int delta_of(const GArgs& a, int code) {
     const int base = a.ctrl->dbase > 0 ? a.ctrl->dbase : 1;
     switch (dc) {
         case DCLS_BASE: return base;
-        case DCLS_WIDE: return base <= (1 << 27) ? base * 8 : (1 << 30);
+        case DCLS_WIDE: return base <= (1 << 24) ? base * 64 : (1 << 30);
         case DCLS_EXPLICIT: return a.sp.delta;
         default: return 0;
     }
@@ -863,6 +866,14 @@ __device__ __forceinline__ int delta_of(const GArgs& a, int code) {
 __device__ int pre_phase(const GArgs& a, int r, int k, GShared& sh) {
     const ListRef in = cl_of(a, r - 1);
     const ListRef out = cl_of(a, r);
+    // the learned schedule's inputs besides the list totals (its weights and
+    // the previous round's record) are read before the totals are scanned
+    MlpLane wl{};
+    SchedHist hprev{};
+    if (a.sp.sched == LLP_SCHED_LEARNED && a.sp.mlp && threadIdx.x < 64) {
+        wl = mlp_load(a.sp.mlp);
+        hprev = a.ctrl->hist[(r + 1) & 1];
+    }
     load_segments(in.seg, a.nseg, sh.cnt, sh.epre, sh.tmp, &sh.tot_edges, &sh.tot_count);
     const int force_dense = (r == 1 && a.warm_dense);
     if (blockIdx.x == 0 && threadIdx.x == 0 && a.trace && r >= 2 && r - 2 < a.trace_cap) {
@@ -899,8 +910,8 @@ __device__ int pre_phase(const GArgs& a, int r, int k, GShared& sh) {
     }
     // schedule decision (identical in every workgroup)
     if (threadIdx.x < 64) {
-        int code = decide_mode(a.sp, a.ctrl->hist[(r + 1) & 1], r, sh.tot_count, sh.tot_edges, a.n, a.m,
-                               force_dense);
+        int code = decide_mode(a.sp, hprev, r, sh.tot_count, sh.tot_edges, a.n, a.m,
+                               force_dense, wl, reinterpret_cast<float*>(sh.own[0]));
         if (threadIdx.x == 0) sh.code = code;
     }
     if (threadIdx.x == 0) {
@@ -1276,16 +1287,10 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
     a.trace_cap = o.trace_cap;
     a.warm_dense = (o.warm_start || jobs_dur) ? 1 : 0;   // jobs: every index is a round-1 candidate
     a.fuse_end = (!(o.flags & LLP_VERIFY) && !jobs_dur) ? 1 : 0;
-    int s = sched_params(o, bfs || jobs_dur || g->out_w != nullptr, &a.sp);
+    const bool can_push = bfs || jobs_dur || g->out_w != nullptr;
+    int s = sched_params(o, can_push, &a.sp);
     if (s) return s;
-    // BFS dense rounds skip the rows already final (dense_cap), so they pay
-    // from a much narrower frontier: the frontier-width rule switches at m / 14
-    // (the direction-optimizing BFS threshold) instead of m / 2; weighted
-    // dense rounds gather only the arcs that pass the arc bound (dense_dmin),
-    // and switch at m / 3 (on R-MAT 22 a dense round costs what a push of
-    // about 0.37 m arcs does)
-    if (bfs) a.sp.dense_frac = 1.0f / 14.0f;
-    else if (!jobs_dur) a.sp.dense_frac = 1.0f / 3.0f;
+    hybrid_params(jobs_dur ? LLP_KIND_JOBS : (bfs ? LLP_KIND_BFS : LLP_KIND_SSSP), g->n, g->m, can_push, &a.sp);
 
     const int per_cu = graph_wgs_per_cu(o.chunk);
     size_t need = graph_ws(g->n, g->m, per_cu, nullptr, nullptr, 0);

@@ -197,15 +197,16 @@ __global__ void k_mlp_adam(const float* g, float* p, float* m1, float* m2, int s
 }
 
 // features[r][12] of traced rounds r = 1..rounds, as the sweep computes them
-// when it decides round r (history from the record of round r-1).
-__global__ void k_trace_features(long long rounds, const llp_trace_rec* tr, int n, int m, float* F) {
+// when it decides round r (history from the record of round r-1; the
+// hybrid's code for the round from the same parameters the sweep uses).
+__global__ void k_trace_features(long long rounds, const llp_trace_rec* tr, int n, int m, SchedParams sp, float* F) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     SchedHist h;
     memset(&h, 0, sizeof(h));
     for (long long r = 1; r <= rounds; ++r) {
         const llp_trace_rec t = tr[r - 1];
         float f[12];
-        round_features(f, (int)r, t.in_count, (int)t.in_edges, n, m, h);
+        round_features(f, (int)r, t.in_count, (int)t.in_edges, n, m, h, hybrid_code(sp, (int)t.in_edges, m));
         for (int k = 0; k < 12; ++k) F[(r - 1) * 12 + k] = f[k];
         const long long prev_adv = h.adv_total;
         h.r = (int)r;
@@ -260,13 +261,18 @@ int llp_mlp_adam(const float* grad, float* params, float* m1, float* m2, int32_t
     return llp::hip_check(hipGetLastError(), "k_mlp_adam");
 }
 
-int llp_trace_features(int64_t rounds, const llp_trace_rec* trace, int32_t n, int64_t m, float* features,
-                       void* stream) {
+int llp_trace_features(int64_t rounds, const llp_trace_rec* trace, int32_t n, int64_t m, int32_t kind,
+                       float* features, void* stream) {
     if (rounds < 0 || n <= 0 || m < 0 || m > 0x7fffffffll || (rounds > 0 && (!trace || !features)))
         return llp::fail(LLP_E_ARG, "bad trace-feature arguments");
+    if (kind != LLP_KIND_SSSP && kind != LLP_KIND_BFS && kind != LLP_KIND_JOBS)
+        return llp::fail(LLP_E_ARG, "kind must be LLP_KIND_SSSP, LLP_KIND_BFS or LLP_KIND_JOBS");
     if (rounds == 0) return LLP_OK;
+    llp::SchedParams sp;
+    memset(&sp, 0, sizeof(sp));
+    llp::hybrid_params(kind, n, m, true, &sp);
     hipLaunchKernelGGL(llp::k_trace_features, dim3(1), dim3(64), 0, (hipStream_t)stream, (long long)rounds, trace, n,
-                       (int)m, features);
+                       (int)m, sp, features);
     return llp::hip_check(hipGetLastError(), "k_trace_features");
 }
 

@@ -39,6 +39,7 @@ int sched_params(const llp_opts& o, bool can_push, SchedParams* sp) {
     sp->can_push = can_push ? 1 : 0;
     sp->seed = o.seed;
     sp->dense_frac = 0.5f;
+    sp->push_dclass = DCLS_NONE;
     if (o.sched == LLP_SCHED_SCRIPT) {
         if (o.plan_len < 0 || (o.plan_len > 0 && !o.plan)) return fail(LLP_E_ARG, "SCRIPT needs plan and plan_len");
         sp->plan = o.plan;
@@ -50,6 +51,23 @@ int sched_params(const llp_opts& o, bool can_push, SchedParams* sp) {
         if (!sp->mlp) return fail(LLP_E_ARG, "LLP_SCHED_LEARNED needs llp_sched_set_weights() first");
     }
     return LLP_OK;
+}
+
+void hybrid_params(int kind, long long n, long long m, bool can_push, SchedParams* sp) {
+    // BFS dense rounds skip the rows already final (the level cap), so they pay
+    // from a much narrower frontier: m / 14 (the direction-optimizing BFS
+    // threshold); weighted dense rounds gather only the arcs that pass the arc
+    // bound and switch at m / 3 (on R-MAT 22 a dense round costs what a push of
+    // about 0.37 m arcs does); jobs at m / 2
+    sp->dense_frac = kind == LLP_KIND_BFS ? 1.0f / 14.0f : (kind == LLP_KIND_SSSP ? 1.0f / 3.0f : 0.5f);
+    sp->can_push = can_push ? 1 : 0;
+    // sparse weighted graphs with several arcs per vertex (a mesh): unbucketed
+    // push rounds re-correct each distance many times (about 200 advances per
+    // vertex on the 4096^2 grid), wide buckets settle it in about five; below
+    // two arcs per vertex (chains) there is little to re-correct and buckets
+    // only add rounds
+    sp->push_dclass =
+        (kind == LLP_KIND_SSSP && can_push && n > 0 && m >= 2 * n && m < 8 * n) ? DCLS_WIDE : DCLS_NONE;
 }
 
 }  // namespace llp

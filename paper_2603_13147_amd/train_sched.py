@@ -1,14 +1,17 @@
 """Train the learned per-round scheduler on the GPU from the sweep's own traces.
 
-For each training graph the plain schedule is run once with LLP_TRACE; the
-round features come from the trace (llp_trace_features, the same function the
-sweep evaluates when it decides a round).  A sample of rounds is labelled by
-measurement: for round r and every candidate round code a (push / pull /
-dense x delta class), the solve is re-run with the script schedule
-(plain for rounds < r, a for rounds r .. r+h-1, plain afterwards) and timed
-on the device; the label is the code with the smallest median time.  The
-network is then fitted with the library's own forward, loss, backward and
-Adam kernels (full batch), and the FP32 master weights are saved as .npy.
+For each training graph several behaviour schedules (plain, push, random and
+the frontier-width hybrid) are run once with LLP_TRACE; the round features
+come from the trace (llp_trace_features, the same function the sweep
+evaluates when it decides a round, the hybrid's own code for the round among
+them).  A sample of rounds is labelled by measurement: for round r and every
+candidate round code a (push / pull / dense x delta class), the solve is
+re-run with the script schedule (the behaviour's codes for rounds < r, a for
+rounds r .. r+h-1, the hybrid's choice afterwards) and timed on the device;
+the label is the fastest code, the hybrid's own choice whenever it is within
+2% of the fastest.  The network is then fitted with the library's own
+forward, loss, backward and Adam kernels (full batch), and the FP32 master
+weights are saved as .npy.
 
 Usage (on a machine with an MI355X):
     python -m paper_2603_13147_amd.train_sched --out sched_weights.npy
@@ -38,6 +41,19 @@ ACTIONS = [PUSH, PLAIN, llp.round_code(llp.MODE_DENSE, llp.DCLASS_NONE),
            llp.round_code(llp.MODE_PUSH, llp.DCLASS_WIDE), llp.round_code(llp.MODE_PUSH, llp.DCLASS_BASE),
            llp.round_code(llp.MODE_PULL, llp.DCLASS_WIDE), llp.round_code(llp.MODE_PULL, llp.DCLASS_BASE)]
 TIE = 0.02
+HYBRID = 3   # script code: the round the frontier-width hybrid would run
+
+
+def hybrid_of(f5):
+    """The hybrid's round code from its feature (0 push, 0.5 push with wide
+    buckets, 0.25 pull, 1 dense)."""
+    if f5 >= 0.75:
+        return llp.round_code(llp.MODE_DENSE, llp.DCLASS_NONE)
+    if f5 >= 0.375:
+        return llp.round_code(llp.MODE_PUSH, llp.DCLASS_WIDE)
+    if f5 >= 0.125:
+        return PLAIN
+    return PUSH
 
 def init_params(seed=0):
     """He-uniform weights, zero biases (float32[LLP_MLP_PARAMS])."""
@@ -74,7 +90,7 @@ def behaviours(seed):
     """Schedules whose rounds are labelled: their histories are what the
     network sees as features when it runs (plain, push and a random mix)."""
     return [("plain", dict(sched=llp.SCHED_PLAIN)), ("push", dict(sched=llp.SCHED_FIXED, flags=llp.PUSH)),
-            ("random", dict(sched=llp.SCHED_RANDOM, seed=seed))]
+            ("random", dict(sched=llp.SCHED_RANDOM, seed=seed)), ("hybrid", dict(sched=llp.SCHED_HYBRID))]
 
 
 def label_graph(name, g, kinds, max_rows, horizon, reps, log, seed=0):
@@ -82,8 +98,9 @@ def label_graph(name, g, kinds, max_rows, horizon, reps, log, seed=0):
 
     Round r of a behaviour schedule is labelled with the round code a whose
     rollout -- the behaviour's own codes for rounds < r, a for rounds
-    r .. r+h-1, push afterwards -- reaches the fixpoint in the least device
-    time."""
+    r .. r+h-1, the hybrid's choice afterwards -- reaches the fixpoint in the
+    least device time (the hybrid's own code for round r when it is within
+    TIE of the least)."""
     import torch
     s = llpgen.max_outdeg_source(g)
     csr = llpgen.CSRGraph(g, weighted=True, out_weights=True)
@@ -103,9 +120,10 @@ def label_graph(name, g, kinds, max_rows, horizon, reps, log, seed=0):
             R = int(st.rounds)
             rec = llp.trace_records(trace, R)
             codes = [int(c) for c in rec["mode"]]
-            F = llp.trace_features(trace, R, g.n, g.m).cpu().numpy()
+            F = llp.trace_features(trace, R, g.n, g.m, llp.KIND_BFS if kind == "bfs" else llp.KIND_SSSP)
+            F = F.cpu().numpy()
             rows = np.arange(1, R + 1) if R <= max_rows else np.unique(np.linspace(1, R, max_rows).astype(int))
-            tail = [PUSH] * (R + 64)
+            tail = [HYBRID] * (2 * R + 20000)   # longer than any rollout: the hybrid to the end
             t0 = time.time()
             counts = {}
             for r in rows:
@@ -115,7 +133,9 @@ def label_graph(name, g, kinds, max_rows, horizon, reps, log, seed=0):
                                         device="cuda")
                     costs.append(timed(fn, dg, s, ws, out, reps, sched=llp.SCHED_SCRIPT, plan=plan))
                 best = min(costs)
-                lab = next(a for a, c in zip(ACTIONS, costs) if c <= best * (1 + TIE))
+                hyb = hybrid_of(float(F[r - 1][5]))
+                near = [a for a, c in zip(ACTIONS, costs) if c <= best * (1 + TIE)]
+                lab = hyb if hyb in near else near[0]
                 X.append(F[r - 1])
                 Y.append(lab)
                 counts[lab] = counts.get(lab, 0) + 1
@@ -167,7 +187,7 @@ def main(argv=None):
     ap.add_argument("--out", required=True)
     ap.add_argument("--rows", type=int, default=16, help="rounds labelled per trace")
     ap.add_argument("--grid-rows", type=int, default=12)
-    ap.add_argument("--horizon", type=int, default=4)
+    ap.add_argument("--horizon", type=int, default=1)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--lr", type=float, default=3e-3)

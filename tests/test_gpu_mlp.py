@@ -115,26 +115,42 @@ def test_training_fits_a_separable_rule():
     assert acc > 0.95
 
 
-def test_learned_decisions_match_trace_features():
+@pytest.mark.parametrize("which", ["rmat13-sssp", "rmat13-bfs", "grid64-sssp"])
+def test_learned_decisions_match_trace_features(which):
     """The decision the sweep takes in round r is the network's output on the
-    features llp_trace_features computes from the trace (same function), and
-    the learned schedule reaches the oracle's fixpoint."""
-    g = llpgen.rmat_graph(13, seed=21)
+    features llp_trace_features computes from the trace (same function, the
+    hybrid's code for the round included: BFS thresholds and the wide
+    buckets of a sparse weighted graph), and the learned schedule reaches the
+    oracle's fixpoint."""
+    g = llpgen.rmat_graph(13, seed=21) if which.startswith("rmat") else llpgen.grid_graph(64, 64, seed=21)
+    bfs = which.endswith("bfs")
     s = llpgen.max_outdeg_source(g)
     dg = llp.DeviceGraph(llpgen.CSRGraph(g, weighted=True, out_weights=True))
     p = rand_params(11, scale=0.8)
     llp.set_sched_weights(p)
     trace = llp.trace_buffer(4096)
     st = llp.Stats()
-    d = llp.sssp(dg, s, sched=llp.SCHED_LEARNED, flags=llp.TRACE, trace=trace, stats=st)
+    fn = llp.bfs if bfs else llp.sssp
+    d = fn(dg, s, sched=llp.SCHED_LEARNED, flags=llp.TRACE, trace=trace, stats=st)
     torch.cuda.synchronize()
-    assert np.array_equal(d.cpu().numpy(), oracle.sssp(g.n, g.src, g.dst, g.w, s, bag=True))
+    want = oracle.sssp(g.n, g.src, g.dst, None if bfs else g.w, s, bag=True)
+    assert np.array_equal(d.cpu().numpy(), want)
     R = int(st.rounds)
     rec = llp.trace_records(trace, R)
-    F = llp.trace_features(trace, R, g.n, g.m)
+    F = llp.trace_features(trace, R, g.n, g.m, llp.KIND_BFS if bfs else llp.KIND_SSSP)
+    # the hybrid's code as a feature: dense above m/3 (SSSP) or m/14 (BFS) out-arcs,
+    # wide buckets for the push rounds of the sparse weighted grid
+    frac = 1 / 14 if bfs else 1 / 3
+    hyb = np.where(rec["in_edges"] > frac * g.m, 1.0, 0.5 if which.startswith("grid") else 0.0)
+    assert np.array_equal(F.cpu().numpy()[:, 5], hyb)
     logits, _ = llp.mlp_forward(torch.tensor(p, device="cuda"), F)
     z = logits.cpu().numpy()
     mode = np.where(z[:, 0] > 0, 2, np.where(z[:, 1] > 0, 1, 0))
     dc = np.argmax(z[:, 2:], axis=1)
-    assert np.array_equal(rec["mode"] & 3, mode)
-    assert np.array_equal((rec["mode"] >> 8) & 3, dc)
+    # rounds of fewer than m / 256 frontier arcs take the hybrid's code
+    gated = rec["in_edges"].astype(np.int64) * 256 < g.m
+    hmode = np.where(hyb == 1.0, 1, 2)
+    hdc = np.where(hyb == 0.5, llp.DCLASS_WIDE, llp.DCLASS_NONE)
+    assert gated.any() and (~gated).any()
+    assert np.array_equal(rec["mode"] & 3, np.where(gated, hmode, mode))
+    assert np.array_equal((rec["mode"] >> 8) & 3, np.where(gated, hdc, dc))
