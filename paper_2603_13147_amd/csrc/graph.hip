@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "llp_host.h"
@@ -51,10 +52,12 @@ struct GCtrl {
     int carried[2];     // entries carried by the delta filter, by round parity (traced solves)
     int step_phase[2];  // step kernel k: phase[k & 1] 0 = PRE of round step_round + 1, 1 = MAIN of step_round
     int step_round[2];
-    int stop[2];        // step launch k returns at once when stop[k & 1] is set (see k_graph_step)
     int diag[8];        // first guard event: site, index, bound, context
     long long rounds, cand, edges, adv, xedges, pedges, gath;
     SchedHist hist[2];  // scheduler history, double-buffered by round parity
+    int stop[2];        // step launch k returns at once when stop[k & 1] is set (see k_graph_step)
+    unsigned tail_bar;  // barrier counter of a tail launch (cleared before each)
+    int tail_rounds;    // rounds run by tail launches
 };
 
 struct GArgs {
@@ -208,7 +211,10 @@ struct GShared {
     union {
         int own[GW][64];      // list iterator: owner slots
         int dcb[GW][DBLK + 192];  // dense blocks: candidate (or row) of each position; per row: bound, first arc, first position
-        int pw[GW][8][64];    // push blocks: entry start, source value, row base, duration; entry of each position
+        struct {
+            int pw[GW][8][64];    // push blocks: entry start, source value, row base, duration; entry of each position
+            int lq_v[512], lq_ob[512], lq_od[512];   // bucketed push rounds: the local queue (see local_drain)
+        };
     };
     unsigned long long ctr;    // appends to the phase's main output list
     unsigned long long cctr;   // PRE in pull rounds: entries carried into CL[r]
@@ -218,6 +224,9 @@ struct GShared {
     int tmp1;
     int carried;
     int tmp[GW + 1];
+    int lq_top;                // entries of the local queue
+    long long lq_arcs;         // arcs the local passes pushed
+    unsigned long long cnt_rd, cnt_gath;   // dense rounds: arcs read, states gathered by the workgroup
 };
 
 // Candidate value pulled through arc (u -> v) of weight w: G[u] - w when u is
@@ -589,6 +598,32 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
 constexpr int PJ = 4;
 constexpr int PBLK = 64 * PJ;
 
+// Local queue of a bucketed push round (the per-worker work bag of the
+// paper's Section 4.3 with its recency preference, per workgroup): a target
+// the workgroup advances to a distance inside the round's bucket, with at
+// most LQ_DEG out-arcs, goes onto a stack in LDS instead of into CL[r], and
+// after its share of the list the workgroup pops the newest entries and
+// pushes their arcs with their current values, queueing again what those
+// advance, for at most LQ_ITERS passes.  What does not fit, and what is left
+// after the last pass, is stamped and appended to CL[r] as usual, so every
+// advanced vertex has its arcs pushed with its final value either here or in
+// a later round.  The bucket bounds how far a pass can run ahead.
+constexpr int LQ_CAP = 512;
+constexpr int LQ_DEG = 8;
+constexpr int LQ_ITERS = 64;
+
+// Queue target x (out-row [ob, ob + od)) if it qualifies and there is room;
+// returns whether it was queued.
+__device__ __forceinline__ bool lq_put(GShared& sh, bool want, int x, int ob, int od) {
+    if (!want) return false;
+    const int slot = atomicAdd(&sh.lq_top, 1);
+    if (slot >= LQ_CAP) return false;
+    sh.lq_v[slot] = x;
+    sh.lq_ob[slot] = ob;
+    sh.lq_od[slot] = od;
+    return true;
+}
+
 // In-round continuation (push rounds): a lane that advanced a target with at
 // most CDEG out-arcs pushes that target's arcs right away with its new
 // value, up to CDEPTH steps deep, instead of leaving it to the next round;
@@ -603,6 +638,7 @@ constexpr int CDEG = 2;
 constexpr int CDEPTH = 32;
 constexpr int CONT_EDGES = 1 << 20;   // rounds with at most this many arcs to push
 
+template <bool COH>
 __device__ void push_continue(const GArgs& a, int r, int cv, int cg, int cob, int cod, long long hi, const ListRef& out,
                               unsigned long long* ctr, bool& ovf, long long& nadv, int& lmin) {
     for (int d = 0; d < CDEPTH; ++d) {
@@ -645,7 +681,7 @@ __device__ void push_continue(const GArgs& a, int r, int cv, int cg, int cob, in
                 }
             }
             if (changed) nadv++;
-            append(changed && yod > 0, y[k], yob, yod, ctr, out, &a.ctrl->status);
+            append<COH>(changed && yod > 0, y[k], yob, yod, ctr, out, &a.ctrl->status);
         }
         cv = nv;
         cg = ng;
@@ -654,13 +690,14 @@ __device__ void push_continue(const GArgs& a, int r, int cv, int cg, int cob, in
     }
 }
 
-template <class Src>
+template <bool COH, bool LQ, class Src>
 __device__ void push_wave(const GArgs& a, const Src& src, int wb, int we, int r, long long hi, const ListRef& out,
                           unsigned long long* ctr, GShared& sh, int (*pw)[64], bool& ovf, long long& nadv,
                           int& lmin) {
     if (wb >= we) return;
     const int l = lane();
-    const bool cont = !a.jobs && src.sv.total_edges <= CONT_EDGES;
+    const bool lq = LQ && hi > 0 && !a.jobs;   // bucketed rounds queue locally instead of continuing
+    const bool cont = !lq && !a.jobs && src.sv.total_edges <= CONT_EDGES;
     Cursor cur = src.locate(wb);
     int base = wb;
     int av = src.avail(cur);
@@ -697,7 +734,7 @@ __device__ void push_wave(const GArgs& a, const Src& src, int wb, int we, int r,
         }
         const bool put = carry && e.z >= base && e.z < limit;
         if (put) amax(&a.cstamp[u], r);
-        append(put, e.x, e.y, e.w, ctr, out, &a.ctrl->status);
+        append<COH>(put, e.x, e.y, e.w, ctr, out, &a.ctrl->status);
         if (put) lmin = min(lmin, LLP_INF - gu);
         const int kc = __popcll(ballot(put));
         if (l == 0 && kc && a.trace) atomicAdd(&sh.carried, kc);
@@ -773,26 +810,122 @@ __device__ void push_wave(const GArgs& a, const Src& src, int wb, int we, int r,
                 if (old < c[j]) {
                     ob = a.out_ptr[x[j]];
                     od = a.out_ptr[x[j] + 1] - ob;
-                    lmin = min(lmin, dist_key(a, c[j]));
-                    if (cont && cv < 0 && od > 0 && od <= CDEG && (hi <= 0 || (long long)(LLP_INF - c[j]) < hi)) {
+                    const bool inb = (long long)(LLP_INF - c[j]) < hi;
+                    if (LQ && lq_put(sh, lq && inb && od > 0 && od <= LQ_DEG, x[j], ob, od)) {
+                        // queued: its arcs are pushed by this workgroup's local passes
+                    } else if (cont && cv < 0 && od > 0 && od <= CDEG && (hi <= 0 || inb)) {
+                        lmin = min(lmin, dist_key(a, c[j]));
                         cv = x[j];
                         cg = c[j];
                         cob = ob;
                         cod = od;
                     } else {
+                        lmin = min(lmin, dist_key(a, c[j]));
                         changed = amax(&a.cstamp[x[j]], r) < r;
                     }
                 }
             }
             if (changed) nadv++;
-            append(changed && od > 0, x[j], ob, od, ctr, out, &a.ctrl->status);
+            append<COH>(changed && od > 0, x[j], ob, od, ctr, out, &a.ctrl->status);
         }
-        if (cont) push_continue(a, r, cv, cg, cob, cod, hi, out, ctr, ovf, nadv, lmin);
+        if (cont) push_continue<COH>(a, r, cv, cg, cob, cod, hi, out, ctr, ovf, nadv, lmin);
         cur = nxt;
         base = limit;
         av = nav;
         e = ne;
     }
+}
+
+// The local passes of a bucketed push round (see LQ_CAP): called by every
+// thread of the workgroup after its share of the list.  Each pass takes up
+// to GB of the newest entries, one per thread, and pushes the entry's
+// out-arcs (at most LQ_DEG) with the vertex's current value.
+template <bool COH>
+__device__ void local_drain(const GArgs& a, int r, long long hi, const ListRef& out, unsigned long long* ctr,
+                            GShared& sh, bool& ovf, long long& nadv, int& lmin) {
+    long long arcs = 0;
+    for (int it = 0;; ++it) {
+        __syncthreads();
+        const int top = min(sh.lq_top, LQ_CAP);
+        if (top == 0) break;
+        // every queued entry may still have to be appended, and a pass can add
+        // LQ_DEG - 1 entries per entry it takes: passes run while the
+        // workgroup's segment of CL[r] can hold that, else the queue is handed
+        // to the list
+        const long long room = (long long)out.cap - (long long)(sh.ctr & 0xffffffffull) - top;
+        int take = min(top, GB);
+        if ((long long)take * (LQ_DEG - 1) > room) take = (int)max(room / (LQ_DEG - 1), 0ll);
+        const bool last = it >= LQ_ITERS || take == 0;
+        if (last) take = top;
+        const int base = top - take;
+        // the thread's entries, read before the stack is shortened and refilled
+        int v[2] = {-1, -1}, ob[2] = {0, 0}, od[2] = {0, 0};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int i = base + threadIdx.x + q * GB;
+            if (i < top) {
+                v[q] = sh.lq_v[i];
+                ob[q] = sh.lq_ob[i];
+                od[q] = sh.lq_od[i];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) sh.lq_top = base;
+        __syncthreads();
+        if (last) {
+            // hand what is left to the next round
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                bool changed = false;
+                if (v[q] >= 0) {
+                    changed = amax(&a.cstamp[v[q]], r) < r;
+                    lmin = min(lmin, dist_key(a, ld_relaxed(&a.G[v[q]])));
+                }
+                if (changed) nadv++;
+                append<COH>(changed, v[q], ob[q], od[q], ctr, out, &a.ctrl->status);
+            }
+            break;
+        }
+        const int gv = v[0] >= 0 ? ld_relaxed(&a.G[v[0]]) : 0;
+        bool bad = false;
+        int x[LQ_DEG], cand[LQ_DEG];
+#pragma unroll
+        for (int k = 0; k < LQ_DEG; ++k) {
+            const bool act = v[0] >= 0 && k < od[0];
+            const int e = act ? clampi(ob[0] + k, a.m, bad) : 0;
+            x[k] = act ? a.out_dst[e] : 0;
+            const int w = act ? (a.unit_w ? 1 : a.out_w[e]) : 0;
+            bool o = false;
+            const int cc = act ? pull_cand(gv, w, o) : 0;
+            ovf |= act && o;
+            cand[k] = cc;
+            arcs += act ? 1 : 0;
+        }
+        int gx[LQ_DEG];
+#pragma unroll
+        for (int k = 0; k < LQ_DEG; ++k) {
+            x[k] = clampi(x[k], a.n, bad);
+            gx[k] = a.G[x[k]];
+        }
+        if (bad) record_diag(a.ctrl->diag, 67, v[0], ob[0], od[0], a.n);
+#pragma unroll
+        for (int k = 0; k < LQ_DEG; ++k) {
+            bool changed = false;
+            int yob = 0, yod = 0;
+            if (cand[k] > 0 && cand[k] > gx[k] && amax(&a.G[x[k]], cand[k]) < cand[k]) {
+                yob = a.out_ptr[x[k]];
+                yod = a.out_ptr[x[k] + 1] - yob;
+                const bool inb = (long long)(LLP_INF - cand[k]) < hi;
+                if (!lq_put(sh, inb && yod > 0 && yod <= LQ_DEG, x[k], yob, yod)) {
+                    lmin = min(lmin, dist_key(a, cand[k]));
+                    changed = amax(&a.cstamp[x[k]], r) < r;
+                }
+            }
+            if (changed) nadv++;
+            append<COH>(changed && yod > 0, x[k], yob, yod, ctr, out, &a.ctrl->status);
+        }
+    }
+    if (arcs) atomicAdd((unsigned long long*)&sh.lq_arcs, (unsigned long long)arcs);
 }
 
 // Delta buckets: an input entry whose vertex lies at distance >= hi is not
@@ -841,9 +974,10 @@ __device__ __forceinline__ void wave_range(int total, int& wb, int& we) {
     we = (int)((long long)total * (w + 1) / W);
 }
 
+template <bool COH = false>
 __device__ __forceinline__ void publish(const ListRef& out, unsigned long long ctr, int cmin) {
-    out.seg[blockIdx.x] = ctr;
-    if (out.segmin) out.segmin[blockIdx.x] = cmin;
+    st_u64<COH>(out.seg + blockIdx.x, ctr);
+    if (out.segmin) st_i32<COH>(out.segmin + blockIdx.x, cmin);
 }
 
 // Delta width of a round code (0: no buckets).
@@ -863,6 +997,7 @@ __device__ __forceinline__ int delta_of(const GArgs& a, int code) {
 // Round r, first phase: consume CL[r-1], decide the round's code, then
 // expand into WL (pull) or push (CL[r]); returns the code of a dense round,
 // whose evaluation follows in the same launch, else -1.  k: step launch.
+template <bool LQ>
 __device__ int pre_phase(const GArgs& a, int r, int k, GShared& sh) {
     const ListRef in = cl_of(a, r - 1);
     const ListRef out = cl_of(a, r);
@@ -919,6 +1054,8 @@ __device__ int pre_phase(const GArgs& a, int r, int k, GShared& sh) {
         sh.cctr = 0ull;
         sh.cmin = LLP_INF;
         sh.carried = 0;
+        sh.lq_top = 0;
+        sh.lq_arcs = 0;
     }
     __syncthreads();
     const int code = sh.code;
@@ -975,10 +1112,16 @@ __device__ int pre_phase(const GArgs& a, int r, int k, GShared& sh) {
         }
     } else {
         int lmin = LLP_INF;
-        push_wave(a, src, wb, we, r, hi, out, &sh.ctr, sh, sh.pw[threadIdx.x >> 6], ovf, nadv, lmin);
+        push_wave<false, LQ>(a, src, wb, we, r, hi, out, &sh.ctr, sh, sh.pw[threadIdx.x >> 6], ovf, nadv, lmin);
+        if constexpr (LQ) {
+            if (hi > 0 && !a.jobs) local_drain<false>(a, r, hi, out, &sh.ctr, sh, ovf, nadv, lmin);
+        }
         if (out.segmin) wave_min_to_lds(true, lmin, &sh.cmin);
         __syncthreads();
-        if (threadIdx.x == 0) publish(out, sh.ctr, sh.cmin);
+        if (threadIdx.x == 0) {
+            publish(out, sh.ctr, sh.cmin);
+            if (sh.lq_arcs) atomicAdd((unsigned long long*)&a.ctrl->pedges, (unsigned long long)sh.lq_arcs);
+        }
     }
     if (threadIdx.x == 0 && sh.carried) atomicAdd(&a.ctrl->carried[r & 1], sh.carried);
     if (__any(ovf) && lane() == 0) st_relaxed(&a.ctrl->ovf, 1);
@@ -1035,6 +1178,8 @@ __device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh
         const bool cont = mode == MODE_PULL && !verify;
         sh.ctr = cont ? out.seg[blockIdx.x] : 0ull;
         sh.cmin = (cont && out.segmin) ? out.segmin[blockIdx.x] : LLP_INF;
+        sh.cnt_rd = 0ull;
+        sh.cnt_gath = 0ull;
     }
     int* own = sh.own[threadIdx.x >> 6];
     bool ovf = false;
@@ -1058,9 +1203,18 @@ __device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh
         int nrd = 0, nins = 0;
         dense_wave(a, rr, wb, we, out, sh, sh.dcb[threadIdx.x >> 6], ovf, nadv, lmin, cap, dlo, nrd, nins);
         if ((cap != LLP_INF || dlo >= 0) && !verify) {
+            // arcs read and states gathered: summed per workgroup in LDS, one
+            // atomic each per workgroup
             const long long rd = wave_sum64(nrd), tot = wave_sum64(nins);
-            if (lane() == 0 && rd) atomicAdd((unsigned long long*)&a.ctrl->edges, (unsigned long long)rd);
-            if (lane() == 0 && tot) atomicAdd((unsigned long long*)&a.ctrl->gath, (unsigned long long)tot);
+            if (lane() == 0) {
+                atomicAdd(&sh.cnt_rd, (unsigned long long)rd);
+                atomicAdd(&sh.cnt_gath, (unsigned long long)tot);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                if (sh.cnt_rd) atomicAdd((unsigned long long*)&a.ctrl->edges, sh.cnt_rd);
+                if (sh.cnt_gath) atomicAdd((unsigned long long*)&a.ctrl->gath, sh.cnt_gath);
+            }
         }
         if (out.segmin) wave_min_to_lds(true, lmin, &sh.cmin);
     } else {
@@ -1099,7 +1253,12 @@ __device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh
 // word: the launch that finds the end (and decodes G, every workgroup its
 // share) sets stop[(k + 1) & 1] for the launches after it, each of which
 // passes it on; a workgroup of the finishing launch that starts late must
-// not see it, or its share of G would be left encoded.
+// not see it, or its share of G would be left encoded.  LQ: the local
+// queues of bucketed push rounds are compiled in (launched when a solve can
+// have bucketed rounds; without them a bucketed push round continues chains
+// instead, and the kernel is smaller, which the dense rounds measurably
+// prefer).
+template <bool LQ>
 __global__ void __launch_bounds__(GB, 4) k_graph_step(GArgs a, int k) {
     __shared__ GShared sh;
     if (ld_relaxed(&a.ctrl->stop[k & 1]) || ld_relaxed(&a.ctrl->status)) {
@@ -1111,12 +1270,190 @@ __global__ void __launch_bounds__(GB, 4) k_graph_step(GArgs a, int k) {
     int r = rr, code;
     if (ph == 0) {
         r = rr + 1;
-        code = pre_phase(a, r, k, sh);
+        code = pre_phase<LQ>(a, r, k, sh);
         if (code < 0) return;
     } else {
         code = a.ctrl->mode;
     }
     main_phase(a, r, 0, k, sh, code);
+}
+
+// --------------------------------------------------------------- tail
+// Multi-round mode for narrow push rounds (the tail of a sweep, and every
+// round of a bucketed sweep on a mesh, where a round pushes a few tens of
+// thousands of arcs and a launch per round costs more than the round).  A
+// cooperative launch of the step kernel's shape in which only the
+// workgroups with blockIdx % TAIL_XCDS == 0 work: workgroups are dispatched
+// round-robin over the XCDs, so these share one XCD's L2.  They run
+// consecutive push rounds separated by a barrier on a counter.  Every list
+// word they exchange within the launch (entries, segment totals and minima)
+// is written and read by agent-scope atomics; states advance by atomicMax
+// and are read by atomic loads where a stale value would be wrong (the value
+// pushed), plain loads only as a precheck.  The barrier is correct wherever
+// the workgroups run; only its speed depends on the placement.  The launch
+// hands back to the step launches at the first round that is not a push
+// round of at most TAIL_EDGES arcs (or that the learned network would
+// decide), after TAIL_ROUNDS rounds, or at the end of the sweep, which it
+// decodes; it reads and writes the step slot k & 1 of the step launch k
+// that follows it.  Every wait is bounded: a barrier that does not complete
+// within TAIL_SPIN polls sets LLP_E_HIP and ends the launch.
+constexpr int TAIL_XCDS = 8;
+constexpr int TAIL_EDGES = 1 << 17;
+constexpr int TAIL_ROUNDS = 4096;
+constexpr int TAIL_SPIN = 1 << 22;
+
+__device__ bool tail_barrier(unsigned* bar, unsigned target, int* status, int* ok) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *ok = 1;
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int spins = 0; __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target;) {
+            if (++spins > TAIL_SPIN || ((spins & 1023) == 0 && ld_relaxed(status))) {
+                set_status(status, LLP_E_HIP);
+                *ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __syncthreads();
+    return *ok != 0;
+}
+
+__global__ void __launch_bounds__(GB, 4) k_graph_tail(GArgs a, int k) {
+    __shared__ GShared sh;
+    if (blockIdx.x % TAIL_XCDS) return;
+    GCtrl* c = a.ctrl;
+    const int P = gridDim.x / TAIL_XCDS, me = blockIdx.x / TAIL_XCDS;
+    const bool lead = me == 0 && threadIdx.x == 0;
+    // no stop check here: the host launches the tail only after reading back a
+    // sweep that has not ended, and a participant that starts after the lead
+    // has found the end (and set the stop word for the next step launch) must
+    // still decode its share
+    if (ld_relaxed(&c->status) || ld_relaxed(&c->step_phase[k & 1]) != 0) return;
+    int r = ld_relaxed(&c->step_round[k & 1]) + 1;
+    const int wave = threadIdx.x >> 6;
+    const long long W = (long long)P * GW, w = (long long)me * GW + wave;
+    for (int t = 0;; ++t, ++r) {
+        const ListRef in = cl_of(a, r - 1);
+        const ListRef out = cl_of(a, r);
+        load_segments<true>(in.seg, a.nseg, sh.cnt, sh.epre, sh.tmp, &sh.tot_edges, &sh.tot_count);
+        if (sh.tot_count == 0) {
+            // the end of the sweep: decode G as the step launch that finds it does
+            if (lead) {
+                c->done = 1;
+                c->last_round = r - 1;
+                st_relaxed(&c->stop[k & 1], 1);
+            }
+            if (a.fuse_end && !ld_relaxed(&c->ovf)) {
+                for (long long v = (long long)me * GB + threadIdx.x; v < a.n; v += (long long)P * GB) {
+                    const int g = ld_relaxed(&a.G[v]);
+                    a.G[v] = g > 0 ? LLP_INF - g : LLP_INF;
+                }
+                if (lead) c->decoded = 1;
+            }
+            return;
+        }
+        if ((long long)r > a.max_rounds) {
+            if (lead) {
+                c->over = 1;
+                c->done = 1;
+                c->last_round = r - 1;
+                st_relaxed(&c->stop[k & 1], 1);
+            }
+            return;
+        }
+        const bool netround = a.sp.sched == LLP_SCHED_LEARNED &&
+                              (long long)sh.tot_edges * LEARNED_MIN_FRAC >= (long long)a.m;
+        if (threadIdx.x < 64) {
+            // history records are not needed: the learned network's rounds hand back
+            SchedHist none{};
+            MlpLane wl{};
+            const int code = netround ? round_code(MODE_PULL, DCLS_NONE)
+                                      : decide_mode(a.sp, none, r, sh.tot_count, sh.tot_edges, a.n, a.m, 0, wl,
+                                                    reinterpret_cast<float*>(sh.own[0]));
+            if (threadIdx.x == 0) {
+                sh.code = code;
+                sh.ctr = 0ull;
+                sh.cmin = LLP_INF;
+                sh.carried = 0;
+                sh.lq_top = 0;
+                sh.lq_arcs = 0;
+            }
+        }
+        __syncthreads();
+        const int code = sh.code;
+        // a round's appends (at most one per arc) must fit the participants' segments
+        const bool fits = 2ll * sh.tot_edges <= (long long)P * out.cap;
+        if ((code & 3) != MODE_PUSH || sh.tot_edges > TAIL_EDGES || !fits || t >= TAIL_ROUNDS) {
+            // hand back: the next step launch runs PRE of round r
+            if (lead) {
+                c->step_phase[k & 1] = 0;
+                c->step_round[k & 1] = r - 1;
+            }
+            return;
+        }
+        // the other workgroups' segments of the output list hold an older
+        // round's totals: cleared in the first two rounds (one per list)
+        if (t < 2) {
+            for (int sg = me * GB + threadIdx.x; sg < a.nseg; sg += P * GB) {
+                if (sg % TAIL_XCDS == 0) continue;
+                st_u64<true>(out.seg + sg, 0ull);
+                st_i32<true>(out.segmin + sg, LLP_INF);
+            }
+        }
+        const int delta = delta_of(a, code);
+        long long hi = 0;
+        if (delta > 0) {
+            const int dmin = load_segmin<true>(in.segmin, a.nseg, &sh.tmp1);
+            hi = ((long long)dmin / delta) * delta + delta;
+        }
+        if (lead) {
+            c->mode = code;
+            c->rounds = r;
+            c->tail_rounds++;
+            c->adv += sh.tot_count;
+            c->pedges += sh.tot_edges;
+            hist_push(c->hist[r & 1], c->hist[(r + 1) & 1], r, MODE_PUSH, sh.tot_count, sh.tot_edges);
+            if (a.trace && r - 1 < a.trace_cap) {
+                if (r >= 2 && r - 2 < a.trace_cap) {
+                    a.trace[r - 2].pending = c->carried[(r - 1) & 1];
+                    c->carried[(r - 1) & 1] = 0;
+                }
+                llp_trace_rec tr;
+                tr.round = r;
+                tr.mode = code;
+                tr.in_count = sh.tot_count;
+                tr.out_count = 0;
+                tr.in_edges = sh.tot_edges;
+                tr.out_edges = 0;
+                tr.bucket = hi > 0 ? (int)(hi - delta) : -1;
+                tr.pending = 0;
+                a.trace[r - 1] = tr;
+            }
+        }
+        SegView sv{in.ent, in.cap, a.nseg, sh.cnt, sh.epre, sh.tot_edges, sh.tot_count};
+        ListSrcT<true> src{sv, c->diag};
+        const int wb = (int)((long long)sh.tot_edges * w / W), we = (int)((long long)sh.tot_edges * (w + 1) / W);
+        bool ovf = false;
+        long long nadv = 0;
+        int lmin = LLP_INF;
+        push_wave<true, true>(a, src, wb, we, r, hi, out, &sh.ctr, sh, sh.pw[wave], ovf, nadv, lmin);
+        if (hi > 0) local_drain<true>(a, r, hi, out, &sh.ctr, sh, ovf, nadv, lmin);
+        wave_min_to_lds(true, lmin, &sh.cmin);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            publish<true>(out, sh.ctr, sh.cmin);
+            if (sh.lq_arcs) atomicAdd((unsigned long long*)&c->pedges, (unsigned long long)sh.lq_arcs);
+        }
+        if (threadIdx.x == 0 && sh.carried) atomicAdd(&c->carried[r & 1], sh.carried);
+        if (__any(ovf) && lane() == 0) st_relaxed(&c->ovf, 1);
+        if (!tail_barrier(&c->tail_bar, (unsigned)(t + 1) * (unsigned)P, &c->status, &sh.tmp1)) return;
+    }
+}
+
+__global__ void k_graph_tail_reset(GCtrl* c) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) c->tail_bar = 0u;
 }
 
 __global__ void __launch_bounds__(GB) k_graph_verify(GArgs a, int r) {
@@ -1241,6 +1578,27 @@ static hipEvent_t timing_event(size_t i) {
     return v[i];
 }
 
+// Whether the device runs cooperative launches (the tail kernel needs all its
+// workgroups resident), asked once per device.
+static bool coop_supported() {
+    static std::map<int, bool> known;
+    static std::mutex mu;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = known.find(dev);
+    if (it != known.end()) return it->second;
+    int v = 0;
+    const bool ok = hipDeviceGetAttribute(&v, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess && v != 0;
+    known[dev] = ok;
+    return ok;
+}
+
+static void launch_step(const GArgs& a, int k, bool lq, hipStream_t st) {
+    if (lq) hipLaunchKernelGGL(k_graph_step<true>, dim3(a.nseg), dim3(GB), 0, st, a, k);
+    else hipLaunchKernelGGL(k_graph_step<false>, dim3(a.nseg), dim3(GB), 0, st, a, k);
+}
+
 static int launch_grid_1d(int64_t work) {
     int64_t g = (work + 255) / 256;
     if (g < 1) g = 1;
@@ -1328,6 +1686,16 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
     int status = LLP_OK;
     bool finished = false;           // overflow check and decode done inside the loop
     std::vector<hipEvent_t> evs;     // LLP_TIMING: one pair around each step launch
+    // the step kernel with local queues where bucketed push rounds can occur
+    const bool lq_kernel = !jobs_dur && (a.sp.push_dclass == DCLS_WIDE || o.sched == LLP_SCHED_RANDOM ||
+                                         o.sched == LLP_SCHED_SCRIPT || (o.sched == LLP_SCHED_FIXED && o.delta > 0));
+    // the multi-round tail: push rounds (hybrid, fixed push, learned), graphs
+    // whose grid splits evenly over the XCDs, a device with cooperative launches
+    bool tail_ok = !jobs_dur && a.nseg % TAIL_XCDS == 0 && a.sp.can_push &&
+                   (o.sched == LLP_SCHED_HYBRID || o.sched == LLP_SCHED_LEARNED ||
+                    (o.sched == LLP_SCHED_FIXED && (o.flags & LLP_PUSH))) && coop_supported();
+    float tail_ms = 0.f;
+    int64_t tail_launches = 0;
     if (timing && a.plog) {
         hipLaunchKernelGGL(k_fill_i8, dim3(launch_grid_1d(a.plog_cap)), dim3(256), 0, st, a.plog, a.plog_cap,
                            (signed char)-1);
@@ -1339,12 +1707,12 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
                 hipEvent_t e1 = timing_event(3 + evs.size());
                 if (!e0 || !e1) return fail(LLP_E_HIP, "hipEventCreate failed");
                 LLP_HIP(hipEventRecord(e0, st));
-                hipLaunchKernelGGL(k_graph_step, dim3(a.nseg), dim3(GB), 0, st, a, (int)k);
+                launch_step(a, (int)k, lq_kernel, st);
                 LLP_HIP(hipEventRecord(e1, st));
                 evs.push_back(e0);
                 evs.push_back(e1);
             } else {
-                hipLaunchKernelGGL(k_graph_step, dim3(a.nseg), dim3(GB), 0, st, a, (int)k);
+                launch_step(a, (int)k, lq_kernel, st);
             }
         }
         // without verification, the step launch that finds the end decodes
@@ -1368,6 +1736,37 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
         if (o.abort_host && *o.abort_host) { status = LLP_E_ABORTED; break; }
         if (k >= max_launches) { status = LLP_E_NOT_CONVERGED; break; }
         if (batch < 64) batch *= 2;
+        // the last round was a narrow push round: run the next rounds in the tail
+        const SchedHist& last = h.hist[h.rounds & 1];
+        if (tail_ok && (h.mode & 3) == MODE_PUSH && last.cl_edges <= TAIL_EDGES) {
+            hipLaunchKernelGGL(k_graph_tail_reset, dim3(1), dim3(64), 0, st, a.ctrl);
+            hipEvent_t t0 = timing ? timing_event(2 + evs.size()) : nullptr;
+            hipEvent_t t1 = timing ? timing_event(3 + evs.size()) : nullptr;
+            if (timing) LLP_HIP(hipEventRecord(t0, st));
+            int kk = (int)k;
+            void* args[] = {&a, &kk};
+            if (hipLaunchCooperativeKernel(k_graph_tail, dim3(a.nseg), dim3(GB), args, 0, st) !=
+                hipSuccess) {
+                (void)hipGetLastError();
+                tail_ok = false;   // the grid cannot be resident at once: step launches only
+                continue;
+            }
+            if (timing) LLP_HIP(hipEventRecord(t1, st));
+            s = readback(st, a.ctrl, &h, sizeof(h));
+            if (s) return s;
+            ++tail_launches;
+            if (timing) {
+                float ms = 0.f;
+                LLP_HIP(hipEventElapsedTime(&ms, t0, t1));
+                tail_ms += ms;
+            }
+            if (h.done && early && h.decoded) finished = true;
+            if (h.status) break;
+            if (h.done) {
+                if (h.over) status = LLP_E_NOT_CONVERGED;
+                break;
+            }
+        }
     }
     if (!finished) {
         if (status == LLP_OK && h.status == 0 && (o.flags & LLP_VERIFY)) {
@@ -1412,7 +1811,8 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
             }
             o.stats->device_ms = ms;
             o.stats->kernel_ms = kms;
-            o.stats->pre_ms = pms;
+            o.stats->pre_ms = pms + tail_ms;   // a tail launch runs push rounds
+            o.stats->pre_launches += tail_launches;
         }
     }
     if (h.diag[0]) {

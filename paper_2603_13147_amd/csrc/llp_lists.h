@@ -20,6 +20,51 @@
 
 namespace llp {
 
+// List words read or written by workgroups of the same launch (the
+// multi-round tail kernel) go through agent-scope atomics, which bypass the
+// caches that are not coherent between compute units; lists that only cross
+// a launch boundary use plain accesses (COH = false).
+template <bool COH>
+__device__ __forceinline__ unsigned long long ld_u64(const unsigned long long* p) {
+    if constexpr (COH) return __hip_atomic_load(const_cast<unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+}
+template <bool COH>
+__device__ __forceinline__ void st_u64(unsigned long long* p, unsigned long long v) {
+    if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+template <bool COH>
+__device__ __forceinline__ int ld_i32(const int* p) {
+    if constexpr (COH) return __hip_atomic_load(const_cast<int*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+}
+template <bool COH>
+__device__ __forceinline__ void st_i32(int* p, int v) {
+    if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+template <bool COH>
+__device__ __forceinline__ int4 ld_ent(const int4* p) {
+    if constexpr (COH) {
+        const unsigned long long* q = reinterpret_cast<const unsigned long long*>(p);
+        const unsigned long long a = ld_u64<true>(q), b = ld_u64<true>(q + 1);
+        return make_int4((int)(unsigned)a, (int)(unsigned)(a >> 32), (int)(unsigned)b, (int)(unsigned)(b >> 32));
+    } else {
+        return *p;
+    }
+}
+template <bool COH>
+__device__ __forceinline__ void st_ent(int4* p, int4 v) {
+    if constexpr (COH) {
+        unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
+        st_u64<true>(q, (unsigned long long)(unsigned)v.x | ((unsigned long long)(unsigned)v.y << 32));
+        st_u64<true>(q + 1, (unsigned long long)(unsigned)v.z | ((unsigned long long)(unsigned)v.w << 32));
+    } else {
+        *p = v;
+    }
+}
+
 struct ListRef {
     int4* ent;                    // nb * cap entries
     unsigned long long* seg;      // nb packed totals
@@ -40,6 +85,7 @@ struct SegView {
 
 // Block-wide scan of the packed segment totals into LDS arrays.
 // lds_cnt[nseg], lds_epre[nseg+1] must be __shared__ buffers.
+template <bool COH = false>
 __device__ inline void load_segments(const unsigned long long* seg, int nseg, int* lds_cnt, int* lds_epre,
                                      int* lds_tmp /* >= blockDim/64 + 1 ints */, int* tot_edges, int* tot_count) {
     const int t = threadIdx.x, nt = blockDim.x;
@@ -52,7 +98,7 @@ __device__ inline void load_segments(const unsigned long long* seg, int nseg, in
         const int i = b + k;
         eds[k] = 0;
         if (k < per && i < e) {
-            unsigned long long x = seg[i];
+            unsigned long long x = ld_u64<COH>(seg + i);
             int c = (int)(x & 0xffffffffull), ed = (int)(x >> 32);
             lds_cnt[i] = c;
             eds[k] = ed;
@@ -134,7 +180,8 @@ struct DenseSrc {
 };
 
 // Segmented list.
-struct ListSrc {
+template <bool COH = false>
+struct ListSrcT {
     SegView sv;
     int* diag;
 
@@ -153,13 +200,13 @@ struct ListSrc {
         while (hi2 - lo2 > 64) {
             int step = (hi2 - lo2 + 63) / 64;
             int probe = lo2 + lane() * step;
-            bool ok = probe < hi2 && base[guard(probe, sv.cap, diag, 21, lo2, hi2)].z <= local;
+            bool ok = probe < hi2 && ld_ent<COH>(base + guard(probe, sv.cap, diag, 21, lo2, hi2)).z <= local;
             int c = __popcll(ballot(ok));
             lo2 = lo2 + (c - 1) * step;
             hi2 = min(lo2 + step, hi2);
         }
         int probe = lo2 + lane();
-        bool ok = probe < hi2 && base[guard(probe, sv.cap, diag, 22, lo2, hi2)].z <= local;
+        bool ok = probe < hi2 && ld_ent<COH>(base + guard(probe, sv.cap, diag, 22, lo2, hi2)).z <= local;
         int c = __popcll(ballot(ok));
         return Cursor{s, guard(lo2 + c - 1, sv.cap, diag, 23, e, local)};
     }
@@ -167,7 +214,7 @@ struct ListSrc {
     __device__ int4 load(const Cursor& c, int l) const {
         int s = guard(c.s, sv.nseg, diag, 24, c.i, l);
         int i = guard(c.i + l, sv.cap, diag, 25, c.s, l);
-        int4 x = sv.ent[(long long)s * sv.cap + i];
+        int4 x = ld_ent<COH>(sv.ent + (long long)s * sv.cap + i);
         x.z += sv.epre[s];
         return x;
     }
@@ -177,6 +224,8 @@ struct ListSrc {
         return c;
     }
 };
+
+using ListSrc = ListSrcT<false>;
 
 // Edge-lane context handed to a phase body.
 struct EdgeCtx {
@@ -258,6 +307,7 @@ __device__ inline void for_edges(const Src& src, int wb, int we, int* own_lds, B
 
 // Append entries to the calling workgroup's segment of `out`.
 // want/entry are per lane; lds_ctr is the workgroup's packed LDS counter.
+template <bool COH = false>
 __device__ inline void append(bool want, int v, int rb, int deg, unsigned long long* lds_ctr, const ListRef& out,
                               int* status) {
     uint64_t m = ballot(want);
@@ -276,7 +326,7 @@ __device__ inline void append(bool want, int v, int rb, int deg, unsigned long l
     if (want) {
         int idx = (int)lo + r;
         int off = (int)hi + incl - d;
-        if (idx < out.cap) out.ent[(long long)blockIdx.x * out.cap + idx] = make_int4(v, rb, off, deg);
+        if (idx < out.cap) st_ent<COH>(out.ent + (long long)blockIdx.x * out.cap + idx, make_int4(v, rb, off, deg));
         else set_status(status, 7);
     }
 }
@@ -291,9 +341,10 @@ __device__ inline void wave_min_to_lds(bool want, int val, int* lds_min) {
 }
 
 // Minimum of seg_min[0..nseg) over the workgroup (every thread gets it).
+template <bool COH = false>
 __device__ inline int load_segmin(const int* seg_min, int nseg, int* lds_tmp1) {
     int x = 0x7fffffff;
-    for (int i = threadIdx.x; i < nseg; i += blockDim.x) x = min(x, seg_min[i]);
+    for (int i = threadIdx.x; i < nseg; i += blockDim.x) x = min(x, ld_i32<COH>(seg_min + i));
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) x = min(x, __shfl_xor(x, d, LLP_WAVE));
     if (threadIdx.x == 0) *lds_tmp1 = 0x7fffffff;

@@ -71,10 +71,19 @@ def solve(kind, g, s, **kw):
     return st, msg, out
 
 
-def report(name, e, s, kind, kw, want):
-    st, msg, got = solve(kind, graph(e), s, **kw)
+def report(name, e, s, kind, kw, want, stats=False):
+    extra = {}
+    if stats:
+        stt = P.Stats()
+        kw = dict(kw)
+        kw["flags"] = kw.get("flags", 0) | P.TIMING
+        st, msg, got = solve(kind, graph(e), s, stats=ctypes.pointer(stt), **kw)
+        extra = {"rounds": int(stt.rounds), "pre_launches": int(stt.pre_launches),
+                 "eval_launches": int(stt.eval_launches)}
+    else:
+        st, msg, got = solve(kind, graph(e), s, **kw)
     print(json.dumps({"case": name, "kind": kind, "source": s, "opts": kw, "status": st, "msg": msg,
-                      "equal": bool(np.array_equal(got, want))}), flush=True)
+                      "equal": bool(np.array_equal(got, want)), **extra}), flush=True)
 
 
 def edge_cases(sources=range(5), scheds=SCHEDS, isolated=True):
@@ -107,6 +116,17 @@ def edge_cases(sources=range(5), scheds=SCHEDS, isolated=True):
             report("isolated", eiso, s, "bfs", kw, oracle.bfs(10, src, dst, s))
 
 
+def tight_segments():
+    """A small graph at the full grid (512 workgroups): each workgroup's list
+    segment holds about 200 entries, and bucketed push rounds (random codes,
+    fixed buckets) advance far more vertices through the local queues than a
+    workgroup's share of the list; every append must still fit."""
+    e = llpgen.uniform_graph(1024, 8192, 1, 100, seed=2)
+    want = oracle.sssp(e.n, e.src, e.dst, e.w, 0)
+    for kw in (dict(sched=P.SCHED_RANDOM, seed=1), dict(sched=P.SCHED_FIXED, flags=P.PUSH, delta=40)):
+        report("tight", e, 0, "sssp", kw, want)
+
+
 def decode_race():
     """4096 vertices (eight 512-vertex decode shares): the launch that finds
     the end decodes G in every workgroup; run in index order, workgroup 0
@@ -117,7 +137,31 @@ def decode_race():
         report("decode", e, 0, "sssp", kw, want)
 
 
+def tail_cases():
+    """Sweeps long enough for the multi-round tail kernel (after the first
+    batch of step launches): a 48 x 48 grid (wide buckets under the hybrid,
+    none under fixed push, explicit ones), a bare weighted cycle (chains),
+    and an R-MAT graph (narrow rounds after dense ones)."""
+    e = llpgen.grid_graph(48, 48, 1, 1000, seed=7)
+    s = llpgen.max_outdeg_source(e)
+    ws, wb = oracle.sssp(e.n, e.src, e.dst, e.w, s, bag=True), oracle.bfs(e.n, e.src, e.dst, s, bag=True)
+    for kw in (dict(sched=P.SCHED_HYBRID), dict(sched=P.SCHED_FIXED, flags=P.PUSH),
+               dict(sched=P.SCHED_FIXED, flags=P.PUSH, delta=300)):
+        report("tail-grid", e, s, "sssp", kw, ws, stats=True)
+    report("tail-grid", e, s, "bfs", dict(sched=P.SCHED_HYBRID), wb, stats=True)
+    c = llpgen.uniform_graph(2000, 0, 1, 100, seed=31)
+    report("tail-chain", c, 0, "sssp", dict(sched=P.SCHED_HYBRID), oracle.sssp(c.n, c.src, c.dst, c.w, 0), stats=True)
+    report("tail-chain", c, 0, "bfs", dict(sched=P.SCHED_FIXED, flags=P.PUSH), oracle.bfs(c.n, c.src, c.dst, 0),
+           stats=True)
+    r = llpgen.rmat_graph(11, seed=5)
+    s = llpgen.max_outdeg_source(r)
+    report("tail-rmat", r, s, "sssp", dict(sched=P.SCHED_HYBRID), oracle.sssp(r.n, r.src, r.dst, r.w, s, bag=True),
+           stats=True)
+    report("tail-rmat", r, s, "bfs", dict(sched=P.SCHED_HYBRID), oracle.bfs(r.n, r.src, r.dst, s, bag=True),
+           stats=True)
+
+
 if __name__ == "__main__":
     {"edge": edge_cases,
-     "edge-wide": lambda: edge_cases(sources=(0, 2), scheds=SCHEDS[:4], isolated=False),
-     "decode": decode_race}[sys.argv[1]]()
+     "edge-wide": lambda: (edge_cases(sources=(0, 2), scheds=SCHEDS[:4], isolated=False), tight_segments()),
+     "decode": decode_race, "tail": tail_cases}[sys.argv[1]]()

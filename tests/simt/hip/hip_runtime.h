@@ -21,6 +21,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <type_traits>
 #include <utility>
 
 #define __global__
@@ -29,7 +30,9 @@
 #define __forceinline__ inline __attribute__((always_inline))
 #define __noinline__ __attribute__((noinline)) inline
 #define __launch_bounds__(...)
-#define __shared__ static
+// every __shared__ variable lives in one section, so that a cooperative
+// launch (all workgroups live at once) can give each workgroup its own copy
+#define __shared__ __attribute__((section("simt_lds"))) static
 #define __align__(x) __attribute__((aligned(x)))
 
 struct dim3 {
@@ -59,10 +62,11 @@ int lane_id();
 enum Op { OP_BALLOT, OP_SHFL, OP_SHFL_UP, OP_SHFL_DOWN, OP_SHFL_XOR, OP_WBAR };
 long long wave_op(int op, long long v, int arg);
 void sync_block();
-void run_launch(dim3 g, dim3 b, void (*tramp)(void*), void* ctx);
+void yield();
+void run_launch(dim3 g, dim3 b, void (*tramp)(void*), void* ctx, bool coop);
 template <class F>
-void launch(dim3 g, dim3 b, F f) {
-    run_launch(g, b, [](void* c) { (*(F*)c)(); }, (void*)&f);
+void launch(dim3 g, dim3 b, F f, bool coop = false) {
+    run_launch(g, b, [](void* c) { (*(F*)c)(); }, (void*)&f, coop);
 }
 }  // namespace simt
 
@@ -133,7 +137,7 @@ static inline unsigned simt_mbcnt_hi(unsigned m, unsigned acc) {
 #define __builtin_amdgcn_mbcnt_hi(m, a) simt_mbcnt_hi((m), (a))
 #define __builtin_amdgcn_fence(...) ((void)0)
 #define __builtin_amdgcn_wave_barrier() ((void)::simt::wave_op(::simt::OP_WBAR, 0, 0))
-#define __builtin_amdgcn_s_sleep(x) ((void)0)
+#define __builtin_amdgcn_s_sleep(x) (::simt::yield())
 #define __builtin_nontemporal_load(p) (*(p))
 #define __builtin_nontemporal_store(v, p) (*(p) = (v))
 
@@ -282,5 +286,23 @@ static inline hipError_t hipEventDestroy(hipEvent_t) { return 0; }
 static inline hipError_t hipEventRecord(hipEvent_t, hipStream_t = 0) { return 0; }
 static inline hipError_t hipEventSynchronize(hipEvent_t) { return 0; }
 static inline hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) { *ms = 0.001f; return 0; }
+enum { hipDeviceAttributeCooperativeLaunch = 1 };
+static inline hipError_t hipDeviceGetAttribute(int* v, int attr, int) {
+    *v = attr == hipDeviceAttributeCooperativeLaunch ? 1 : 0;
+    return 0;
+}
+// Cooperative launch: every workgroup of the grid is live at once (the
+// emulation interleaves them), and each calls the kernel with the arguments
+// the pointers in args refer to.
+template <class... A, size_t... I>
+static inline void simt_coop_impl(void (*k)(A...), dim3 g, dim3 b, void** args, std::index_sequence<I...>) {
+    ::simt::launch(g, b, [=]() { k(*static_cast<std::decay_t<A>*>(args[I])...); }, true);
+}
+template <class... A>
+static inline hipError_t simt_coop(void (*k)(A...), dim3 g, dim3 b, void** args) {
+    simt_coop_impl(k, g, b, args, std::index_sequence_for<A...>{});
+    return 0;
+}
+#define hipLaunchCooperativeKernel(k, g, b, args, sm, st) simt_coop(k, dim3(g), dim3(b), (args))
 
 #define hipLaunchKernelGGL(k, g, b, sm, st, ...) ::simt::launch(dim3(g), dim3(b), [=]() { k(__VA_ARGS__); })

@@ -270,7 +270,8 @@ def test_chain_rounds(kind):
         assert rec["round"].tolist() == list(range(1, R + 1))
         assert np.all(rec["mode"] & 3 == llp.MODE_PUSH) and np.all(rec["in_count"] == 1)
         assert np.all((rec["mode"] >> 8) == llp.DCLASS_NONE)
-        assert st.eval_launches == 0 and st.pre_launches == R   # one launch per push round
+        # one step launch per push round, or one multi-round tail launch for many
+        assert st.eval_launches == 0 and st.pre_launches <= R
 
 
 DELTA_SCHEDS = [dict(sched=llp.SCHED_FIXED, delta=d) for d in (1, 16, 64, 255, 4000)] + [

@@ -48,9 +48,11 @@ def test_degenerate_graphs_full_grid(simt_lib):
     """The same graphs with 512 workgroups per launch, as on the MI355X (far
     more list segments and waves than arcs): n = 1, and the 5-vertex graph
     from a source with duplicate arcs and from one with zero-weight arcs
-    under the plain, dense, push and hybrid schedules."""
+    under the plain, dense, push and hybrid schedules; and bucketed push
+    rounds whose local queues advance more vertices than a workgroup's list
+    segment was sized for."""
     rows = run_cases("edge-wide", 256)
-    assert len(rows) == 2 + 2 * 4 * 2
+    assert len(rows) == 2 + 2 * 4 * 2 + 2
     bad = [r for r in rows if r["status"] != 0 or not r["equal"]]
     assert not bad, bad[:5]
 
@@ -59,3 +61,26 @@ def test_decode_by_every_workgroup(simt_lib):
     rows = run_cases("decode", 8)
     assert len(rows) == 2
     assert all(r["status"] == 0 and r["equal"] for r in rows), rows
+
+
+def test_tail_rounds_and_local_queues(simt_lib):
+    """The multi-round tail kernel (a cooperative launch whose workgroups run
+    consecutive push rounds between barriers, here 4 of them interleaved by
+    the emulation) takes over once a sweep outlasts the first batch of step
+    launches with narrow push rounds; bucketed push rounds drain their
+    bucket through each workgroup's local queue.  On a grid (hybrid with wide
+    buckets, fixed push, explicit buckets, BFS) and a bare cycle every
+    output equals the oracle's; the unbucketed long sweeps run most rounds in
+    one tail launch, and the hybrid's bucketed sweep of the grid needs only
+    a few rounds."""
+    rows = run_cases("tail", 16)
+    assert len(rows) == 8
+    assert all(r["status"] == 0 and r["equal"] for r in rows), [r for r in rows if not r["equal"]]
+    long = [r for r in rows if r["case"] in ("tail-grid", "tail-chain") and "delta" not in r["opts"]
+            and not (r["case"] == "tail-grid" and r["kind"] == "sssp" and r["opts"]["sched"] == 3)]
+    assert len(long) == 4
+    assert all(r["pre_launches"] <= 17 and r["rounds"] > 40 for r in long), long
+    hyb = [r for r in rows if r["case"] == "tail-grid" and r["kind"] == "sssp" and r["opts"]["sched"] == 3][0]
+    assert hyb["rounds"] <= 8, hyb
+    dlt = [r for r in rows if "delta" in r["opts"]][0]
+    assert dlt["rounds"] <= 100, dlt
