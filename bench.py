@@ -70,6 +70,14 @@ def parse():
                         "dense round)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only copy a 1 GiB device buffer 3 times (reference for rocprofv3 byte counters)")
+    p.add_argument("--calibrate-gather", action="store_true",
+                   help="only gather 2^25 4-byte values at random and in order from a 16 MB and a 4 GiB "
+                        "table, twice each (what rocprofv3 byte counters read per random gather)")
+    p.add_argument("--summarize-profile", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                   help="summarise rocprofv3 output directories of --profile-steps runs (each holding the "
+                        "round log written with --round-log as round_log.json) and of --calibrate-copy runs: "
+                        "per-phase launches, durations and byte counters of the step kernel; writes the "
+                        "traffic record the bench reads and prints a Markdown table (no GPU needed)")
     return p.parse_args()
 
 
@@ -224,6 +232,142 @@ def committed_traffic(phase):
     return ph["traffic_bytes_per_launch"] if (h == rec["source_sha16"] and ph) else None
 
 
+def _csv_rows(d, suffix):
+    """Rows of the rocprofv3 CSV file ending in suffix under directory d."""
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not files:
+        raise SystemExit(f"no *{suffix} under {d}")
+    with open(files[0], newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _dispatches(d):
+    """(dispatch id, kernel name, duration us or None, {counter: value}) per
+    dispatch, in dispatch order, from a kernel trace or a counter collection."""
+    import glob
+    recs = {}
+    if glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in _csv_rows(d, "counter_collection.csv"):
+            k = int(r["Dispatch_Id"])
+            e = recs.setdefault(k, [k, r["Kernel_Name"], None, {}])
+            e[3][r["Counter_Name"]] = e[3].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    else:
+        for r in _csv_rows(d, "kernel_trace.csv"):
+            k = int(r["Dispatch_Id"])
+            recs[k] = [k, r["Kernel_Name"], (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3, {}]
+    return [recs[k] for k in sorted(recs)]
+
+
+def step_phases(d):
+    """Phase of every step-kernel dispatch of the event-timed solves of a
+    --profile-steps run: the solves are cut at k_graph_init, the last ones
+    paired with the round log, and each solve's step launches before its
+    first multi-round (tail) launch mapped to its rounds in order (a push
+    round one PRE launch, a dense round one MAIN launch, a pull round PRE then
+    MAIN; launches past the last round are no-ops).  Returns {phase: [dispatch]}
+    with phases pre, main, tail (the multi-round launches) and after_tail
+    (step launches after one, not mapped)."""
+    import re
+    log = json.load(open(os.path.join(d, "round_log.json")))
+    solves, cur = [], None
+    for rec in _dispatches(d):
+        name = rec[1]
+        if "k_graph_init" in name:
+            cur = []
+            solves.append(cur)
+        elif cur is not None and ("k_graph_step" in name or re.search(r"k_graph_tail\b(?!_)", name)):
+            cur.append(rec)
+    if len(solves) < len(log):
+        raise SystemExit(f"{d}: {len(solves)} solves traced, {len(log)} in the round log")
+    out = {"pre": [], "main": [], "tail": [], "after_tail": []}
+    for launches, ent in zip(solves[-len(log):], log):
+        want = []
+        for code in ent["modes"]:
+            mode = code & 3
+            want += ["pre", "main"] if mode == 0 else (["main"] if mode == 1 else ["pre"])
+        i = 0
+        for j, rec in enumerate(launches):
+            if "k_graph_tail" in rec[1]:
+                out["tail"].append(rec)
+                out["after_tail"] += [x for x in launches[j + 1:] if "k_graph_step" in x[1]]
+                out["tail"] += [x for x in launches[j + 1:] if "k_graph_tail" in x[1]]
+                break
+            if i < len(want):
+                out[want[i]].append(rec)
+                i += 1
+    return out
+
+
+def summarize_profile(dirs):
+    """Per-phase figures of the step kernel from rocprofv3 runs; writes
+    profiles/k_graph_step_rmat22_hybrid.traffic.json."""
+    import hashlib
+    trace, fetch, write, cfetch, cwrite = dirs
+    copied = 1 << 30   # --calibrate-copy: 2^28 int32 per copy
+
+    def copy_kib(d, counter):
+        v = [r[3][counter] for r in _dispatches(d) if counter in r[3] and "copy" in r[1].lower()]
+        v = v or [r[3][counter] for r in _dispatches(d) if counter in r[3]]
+        return float(np.median(v))
+    fs = copied / (copy_kib(cfetch, "FETCH_SIZE") * 1024)
+    ws_ = copied / (copy_kib(cwrite, "WRITE_SIZE") * 1024)
+    pt, pf, pw = step_phases(trace), step_phases(fetch), step_phases(write)
+    csrc = os.path.join(ROOT, "paper_2603_13147_amd", "csrc")
+    h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                for f in KERNEL_SOURCES)).hexdigest()[:16]
+    phases = {}
+    print("| phase | launches | trace avg us | FETCH_SIZE KiB / launch | WRITE_SIZE KiB / launch | "
+          "HBM traffic / launch |")
+    print("|---|---|---|---|---|---|")
+    for ph in ("pre", "main", "tail", "after_tail"):
+        if not pt[ph]:
+            continue
+        us = float(np.mean([r[2] for r in pt[ph]]))
+        fk = float(np.mean([r[3]["FETCH_SIZE"] for r in pf[ph]])) if pf[ph] else 0.0
+        wk = float(np.mean([r[3]["WRITE_SIZE"] for r in pw[ph]])) if pw[ph] else 0.0
+        fb, wb = int(fk * 1024 * fs), int(wk * 1024 * ws_)
+        phases[ph] = {"launches_traced": len(pt[ph]), "avg_us_trace": round(us, 2),
+                      "fetch_kib_per_launch": round(fk, 1), "write_kib_per_launch": round(wk, 1),
+                      "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                      "traffic_bytes_per_launch": fb + wb}
+        print(f"| {ph.upper()} | {len(pt[ph])} | {us:.2f} | {fk:.0f} | {wk:.0f} | {(fb + wb) / 1e6:.1f} MB |")
+    rec = {"kernel": "k_graph_step", "workload": "rmat22 sssp+bfs hybrid", "source_sha16": h,
+           "fetch_scale": round(fs, 4), "write_scale": round(ws_, 4), "phases": phases}
+    path = os.path.join(ROOT, "profiles", "k_graph_step_rmat22_hybrid.traffic.json")
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(f"\ncopy scale factors: FETCH_SIZE {fs:.4f}, WRITE_SIZE {ws_:.4f}; sources {h}; wrote {path}")
+
+
+def calibrate_gather(torch):
+    """2^25 random and in-order 4-byte gathers (torch.take, int64 indices)
+    from a 16 MB table (the R-MAT 22 state array's size: larger than an XCD's
+    L2, within the Infinity Cache) and a 4 GiB one (beyond both); two of each.
+    Dispatch order: per table, randint, arange, remainder, then take(random),
+    take(in order) twice."""
+    n = 1 << 25
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    res = []
+    for name, tn in (("16MB", 1 << 22), ("4GiB", 1 << 30)):
+        t = torch.ones(tn, dtype=torch.int32, device="cuda")
+        ridx = torch.randint(0, tn, (n,), device="cuda", generator=g)
+        sidx = torch.arange(n, device="cuda") % tn
+        torch.cuda.synchronize()
+        for _ in range(2):
+            for kind, idx in (("random", ridx), ("in_order", sidx)):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                torch.take(t, idx)
+                e1.record()
+                torch.cuda.synchronize()
+                res.append({"table": name, "kind": kind, "ms": round(e0.elapsed_time(e1), 4)})
+        del t, ridx, sidx
+    print(json.dumps({"gathers_per_launch": n, "index_bytes": 8, "launches": res}), flush=True)
+
+
 def time_steps(llp, dg, src, ws, dist, lev, kw, steps, warm, torch, log=None):
     """Wall time per step over `steps` steps without per-launch events, then
     the same number of steps with LLP_TIMING for the kernel counters (their
@@ -243,6 +387,9 @@ def time_steps(llp, dg, src, ws, dist, lev, kw, steps, warm, torch, log=None):
 
 def main():
     a = parse()
+    if a.summarize_profile:
+        summarize_profile(a.summarize_profile)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "the bench runs on one GPU (the sweep does not shard); --gpus above 1 is not supported",
                           "n_gpus": a.gpus}))
@@ -254,6 +401,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    if a.calibrate_gather:
+        calibrate_gather(torch)
+        return
     if a.calibrate_copy:
         x = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
         y = torch.empty_like(x)

@@ -1303,6 +1303,9 @@ constexpr int TAIL_ROUNDS = 4096;
 constexpr int TAIL_SPIN = 1 << 22;
 
 __device__ bool tail_barrier(unsigned* bar, unsigned target, int* status, int* ok) {
+    // every memory operation of the round, atomics without a used result and
+    // atomic stores included, has completed before the count moves
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
         *ok = 1;

@@ -220,7 +220,24 @@ struct ListSrcT {
     }
     __device__ Cursor advance(Cursor c, int k) const {
         c.i += k;
-        while (c.s < sv.nseg && c.i >= min(sv.cnt[c.s], sv.cap)) { c.s++; c.i = 0; }
+        if (c.s < sv.nseg && c.i >= min(sv.cnt[c.s], sv.cap)) {
+            // past this segment: jump to the one holding the next edge, the
+            // last segment whose edge prefix is at most that edge's index
+            // (every entry has arcs, so the empty segments in between share
+            // its prefix).  A narrow list leaves most segments empty, and
+            // stepping over them one at a time cost the wave that finished
+            // the list several microseconds per round.
+            const int e = sv.epre[c.s + 1];
+            int lo = c.s + 1, hi = sv.nseg;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (sv.epre[mid] <= e) lo = mid; else hi = mid;
+            }
+            c.s = lo;
+            c.i = 0;
+            // no edge after this segment: the trailing segments are empty
+            if (c.s < sv.nseg && min(sv.cnt[c.s], sv.cap) == 0) c.s = sv.nseg;
+        }
         return c;
     }
 };

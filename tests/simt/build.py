@@ -1,4 +1,5 @@
-"""Builds the graph sweep (graph.hip and the host code of libllp) against the
+"""Builds the graph sweep and the job readiness sweep (graph.hip, jobs.hip
+and the host code of libllp) against the
 CPU emulation in tests/simt/hip/hip_runtime.h into tests/simt/_build/
 libllp_simt.so, with AddressSanitizer when the host compiler has it.  Test
 infrastructure only: the product library is built by paper_2603_13147_amd/_build.py."""
@@ -12,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_2603_13147_amd", "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT, "libllp_simt.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("graph.hip", "llp_host.cpp", "sched_host.cpp", "abi.cpp")] + \
+SOURCES = [os.path.join(CSRC, f) for f in ("graph.hip", "jobs.hip", "llp_host.cpp", "sched_host.cpp", "abi.cpp")] + \
           [os.path.join(HERE, f) for f in ("simt.cpp", "stubs.cpp")]
 
 

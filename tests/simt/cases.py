@@ -26,6 +26,7 @@ L.llp_workspace_bytes.restype = ctypes.c_size_t
 L.llp_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]
 for fn in (L.llp_solve_sssp, L.llp_solve_bfs):
     fn.argtypes = [ctypes.POINTER(P.Graph), ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(P.Opts)]
+L.llp_solve_jobs.argtypes = [ctypes.c_int32] + [ctypes.c_void_p] * 6 + [ctypes.POINTER(P.Opts)]
 
 SCHEDS = [dict(sched=P.SCHED_PLAIN), dict(sched=P.SCHED_FIXED, flags=P.DENSE),
           dict(sched=P.SCHED_FIXED, flags=P.PUSH), dict(sched=P.SCHED_HYBRID),
@@ -161,7 +162,76 @@ def tail_cases():
            stats=True)
 
 
+def solve_jobs(pred_ptr, pred_idx, dur, **kw):
+    """One readiness sweep (LLP_JOBS_PULL off) on emulated device copies."""
+    n = int(dur.shape[0])
+    succ_ptr, succ_idx = llpgen.job_succ(pred_ptr, pred_idx)
+    o = P.Opts()
+    o.size = ctypes.sizeof(P.Opts)
+    stt = P.Stats()
+    o.stats = ctypes.pointer(stt)
+    for k, v in kw.items():
+        setattr(o, k, v)
+    bufs = [dev(x) for x in (pred_ptr, pred_idx, dur, succ_ptr, succ_idx)]
+    outp = L.simt_alloc(4 * n)
+    st = L.llp_solve_jobs(n, *bufs, outp, ctypes.byref(o))
+    out = np.frombuffer((ctypes.c_char * (4 * n)).from_address(outp), np.int32).copy()
+    msg = L.llp_last_error().decode()
+    for b in bufs + [outp]:
+        if b:
+            L.simt_free(b)
+    return st, msg, out, int(stt.rounds)
+
+
+def report_jobs(name, pred_ptr, pred_idx, dur, **kw):
+    want_st, want = 0, None
+    try:
+        want = oracle.jobs(pred_ptr, pred_idx, dur, bag=True)
+    except Exception as e:  # a cycle or an overflow: the oracle raises
+        want_st = str(e)
+    st, msg, got, rounds = solve_jobs(pred_ptr, pred_idx, dur, **kw)
+    print(json.dumps({"case": name, "kind": "jobs", "opts": kw, "status": st, "msg": msg,
+                      "equal": bool(want is not None and np.array_equal(got, want)), "oracle_error": want_st,
+                      "rounds": rounds}), flush=True)
+
+
+def chain_dag(n, dur=1):
+    pred_ptr = np.concatenate([[0], np.arange(n, dtype=np.int32)]).astype(np.int32)
+    return pred_ptr, np.arange(n - 1, dtype=np.int32), np.full(n, dur, np.int32)
+
+
+def diamond_dag(head=50, width=10000, tail=50):
+    """A chain of head jobs, the last with width successors, all of which
+    precede one job, then a chain of tail jobs: narrow levels, two levels of
+    width arcs, narrow levels again."""
+    preds = [[]] + [[j - 1] for j in range(1, head)]
+    preds += [[head - 1]] * width
+    preds += [list(range(head, head + width))]
+    preds += [[head + width + i] for i in range(tail)]
+    pp = np.concatenate([[0], np.cumsum([len(p) for p in preds])]).astype(np.int32)
+    pi = np.array([x for p in preds for x in p], np.int32)
+    d = llpgen.uniform_ints(len(preds), 1, 100, seed=12).astype(np.int32)
+    return pp, pi, d
+
+
+def job_cases():
+    """The readiness sweep, one launch per level: one job; a 300-job chain
+    (300 levels, one job each, most list segments empty); a random DAG; a
+    chain under a round limit it passes; a cycle behind a chain; a
+    completion time beyond int32; narrow, wide and narrow levels in turn."""
+    report_jobs("one", np.array([0, 0], np.int32), np.zeros(0, np.int32), np.array([5], np.int32))
+    report_jobs("chain", *chain_dag(300, 3))
+    pp, pi, d = llpgen.job_dag(3000, 4.0, 1, 1000, seed=9)
+    report_jobs("dag", pp, pi, d)
+    report_jobs("limit", *chain_dag(100), max_rounds=50)
+    pp, pi, d = chain_dag(40)
+    pp[0:3], pi = np.array([0, 1, 2], np.int32), np.concatenate([[2], pi[1:]]).astype(np.int32)
+    report_jobs("cycle", pp, pi, d)
+    report_jobs("overflow", *chain_dag(20, 1 << 28))
+    report_jobs("diamond", *diamond_dag())
+
+
 if __name__ == "__main__":
     {"edge": edge_cases,
      "edge-wide": lambda: (edge_cases(sources=(0, 2), scheds=SCHEDS[:4], isolated=False), tight_segments()),
-     "decode": decode_race, "tail": tail_cases}[sys.argv[1]]()
+     "decode": decode_race, "tail": tail_cases, "jobs": job_cases}[sys.argv[1]]()

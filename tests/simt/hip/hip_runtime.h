@@ -138,6 +138,7 @@ static inline unsigned simt_mbcnt_hi(unsigned m, unsigned acc) {
 #define __builtin_amdgcn_fence(...) ((void)0)
 #define __builtin_amdgcn_wave_barrier() ((void)::simt::wave_op(::simt::OP_WBAR, 0, 0))
 #define __builtin_amdgcn_s_sleep(x) (::simt::yield())
+#define __builtin_amdgcn_s_waitcnt(x) ((void)(x))
 #define __builtin_nontemporal_load(p) (*(p))
 #define __builtin_nontemporal_store(v, p) (*(p) = (v))
 

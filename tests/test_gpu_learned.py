@@ -54,12 +54,16 @@ def test_learned_gain_on_heldout_graphs(which):
     ws = llp.workspace(llp.KIND_SSSP, g.n, g.m)
     o1 = torch.empty(g.n, dtype=torch.int32, device="cuda")
     o2 = torch.empty(g.n, dtype=torch.int32, device="cuda")
-    reps = 5 if which.startswith("rmat") else 3
-    t_plain = best_ms(dg, s, ws, o1, reps)
-    t_hybrid = best_ms(dg, s, ws, o2, reps, sched=llp.SCHED_HYBRID)
-    assert torch.equal(o1, o2)
-    t_learned = best_ms(dg, s, ws, o2, reps, sched=llp.SCHED_LEARNED)
-    assert torch.equal(o1, o2)
+    t_plain = best_ms(dg, s, ws, o1, 5 if which.startswith("rmat") else 2)
+    # the two schedules alternate, so that drift of the clock or the memory
+    # system over the run falls on both; medians of 7
+    th, tl = [], []
+    for _ in range(7):
+        th.append(best_ms(dg, s, ws, o2, 1, sched=llp.SCHED_HYBRID))
+        assert torch.equal(o1, o2)
+        tl.append(best_ms(dg, s, ws, o2, 1, sched=llp.SCHED_LEARNED))
+        assert torch.equal(o1, o2)
+    t_hybrid, t_learned = float(np.median(th)), float(np.median(tl))
     certify(g, s, o1.cpu().numpy())
     print(f"{which}: plain {t_plain:.3f} ms, hybrid {t_hybrid:.3f} ms, learned {t_learned:.3f} ms")
     assert t_learned < t_plain / 1.1

@@ -172,6 +172,22 @@ def test_jobs_chain_and_isolated():
     assert run_jobs(np.zeros(6, np.int32), np.zeros(0, np.int32), z + 3).tolist() == [0] * 5
 
 
+def test_jobs_long_chain_and_round_limit():
+    # 9000 levels, one job each: launch batches up to their largest size, most list segments empty
+    n = 9000
+    pp = np.concatenate([[0, 0], np.arange(1, n, dtype=np.int32)]).astype(np.int32)
+    pi = np.arange(0, n - 1, dtype=np.int32)
+    d = llpgen.uniform_ints(n, 0, 100, seed=9).astype(np.int32)
+    want = oracle.jobs(pp, pi, d)
+    st = llp.Stats()
+    assert np.array_equal(run_jobs(pp, pi, d, stats=st), want)
+    assert st.rounds == n - 1
+    # a round limit below the depth ends the sweep with LLP_E_NOT_CONVERGED
+    with pytest.raises(llp.LLPError) as e:
+        run_jobs(pp, pi, d, max_rounds=100)
+    assert e.value.status == llp.E_NOT_CONVERGED
+
+
 def cyclic_jobs():
     # 0 -> 1 -> 2 -> 0 plus 3 <- 2
     preds = {0: [2], 1: [0], 2: [1], 3: [2]}
