@@ -331,7 +331,11 @@ int llp_sched_set_weights(const float* params);
    backward: given dlogits[B][5] fp32, accumulate grad[LLP_MLP_PARAMS] fp32;
    loss: BCE on outputs 0-1 against label bits, softmax cross-entropy on 2..4
      against the delta class; writes dlogits and loss[1];
-   step: Adam on fp32 master params (and refreshes their bf16 copy). */
+   step: Adam on fp32 master params (and refreshes their bf16 copy).
+   Forward products run on the matrix cores in BF16 with FP32 accumulation
+   (the network's own arithmetic); backward products in FP32, since the
+   straight-through gradients stay unrounded.  Results agree with a
+   sequential FP32 evaluation up to the order of the FP32 sums. */
 int llp_mlp_forward(int32_t B, const float* params, const float* x, float* logits, uint16_t* act,
                     void* stream);
 int llp_mlp_loss(int32_t B, const float* logits, const int32_t* labels, float* dlogits, float* loss,

@@ -5,10 +5,20 @@
 // Weights are kept in FP32 (master copy) and used as BF16 (round to nearest
 // even) in every product; inputs and hidden activations are rounded to BF16;
 // accumulation is FP32.  The outputs are a push logit, a dense logit and
-// three delta-class logits.  One wave evaluates one row, lane j owning hidden
-// unit j in both layers; the backward pass keeps each lane's gradient rows in
-// registers across the rows of its wave, reduces the waves of a workgroup in
-// LDS and adds one value per parameter and workgroup to the global gradient.
+// three delta-class logits.
+//
+// Both training passes run on the matrix cores, one wave per tile of 16
+// rows.  The forward pass is three BF16 products with FP32 accumulation
+// (v_mfma_f32_16x16x16_bf16): the BF16 inputs and weights are exactly the
+// values the network defines, and the products of two BF16 values are exact
+// in FP32.  Each hidden layer goes through the wave's LDS tile between the
+// accumulator layout of one product and the operand layout of the next.
+// The backward pass keeps the gradient signals in FP32 (the straight-through
+// rule passes them unrounded), so its products are FP32 ones
+// (v_mfma_f32_16x16x4_f32): dH2 = dL W3, dH1 = dZ2 W2, and the weight
+// gradients dZ^T H summed over the wave's tiles in accumulators; the waves
+// of a workgroup are reduced in LDS and each workgroup adds one value per
+// parameter to the global gradient.
 //
 // The features of a traced round are computed by the same device function the
 // sweep uses when it decides that round, so a network trained on trace
@@ -30,40 +40,120 @@ __device__ __forceinline__ float bfw(const float* p, int i) { return round_bf16(
 
 constexpr int MB = 256;            // threads per workgroup
 constexpr int MW = MB / LLP_WAVE;  // waves per workgroup
+constexpr int MT = 16;             // rows per tile (the matrix products' M)
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Operand layouts of the two products, for lane l (wave64):
+//   16x16x16 bf16: A[i][k] at i = l % 16, k = 4 (l / 16) + q (q = 0..3);
+//                  B[k][j] at k = 4 (l / 16) + q, j = l % 16
+//   16x16x4 f32:   A[i][k] at i = l % 16, k = l / 16; B[k][j] at k = l / 16, j = l % 16
+//   both:          D[i][j] at i = 4 (l / 16) + q, j = l % 16
+__device__ __forceinline__ f32x4 mma_bf16(bf16x4 a, bf16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mma_f32(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ short bfbits(float f) { return (short)f32_to_bf16(f); }
 
 // act[row][0..63] = h1, act[row][64..127] = h2 (bf16 bits)
 __global__ void __launch_bounds__(MB) k_mlp_forward(int B, const float* P, const float* X, float* logits,
                                                     unsigned short* act) {
-    const int j = lane();
-    const int wave = blockIdx.x * MW + (threadIdx.x >> 6);
-    const int nw = gridDim.x * MW;
-    // this lane's weights as bf16-valued floats
-    float w1[NI], w2[NH], w3[NO];
+    __shared__ unsigned short hs[MW][MT * NH];   // one wave's hidden tile, row-major
+    const int l = lane(), w = threadIdx.x >> 6;
+    const int lr = l & 15, lg = l >> 4;          // operand row / column, and k group
+    unsigned short* h = hs[w];
+    // B operands (the transposed weights), as bf16
+    bf16x4 bw1[4], bw2[4][4], bw3[4];
 #pragma unroll
-    for (int k = 0; k < NI; ++k) w1[k] = bfw(P, OFF_W1 + j * NI + k);
+    for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-    for (int k = 0; k < NH; ++k) w2[k] = bfw(P, OFF_W2 + j * NH + k);
+        for (int q = 0; q < 4; ++q) {
+            const int k = 4 * lg + q, j = nt * 16 + lr;
+            bw1[nt][q] = k < NI ? bfbits(P[OFF_W1 + j * NI + k]) : (short)0;
+        }
 #pragma unroll
-    for (int o = 0; o < NO; ++o) w3[o] = bfw(P, OFF_W3 + o * NH + j);
-    const float b1 = bfw(P, OFF_B1 + j), b2 = bfw(P, OFF_B2 + j);
-    for (int row = wave; row < B; row += nw) {
-        const float* x = X + (long long)row * NI;
-        float a = b1;
+    for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
-        for (int k = 0; k < NI; ++k) a += w1[k] * round_bf16(x[k]);
-        const float h1 = round_bf16(fmaxf(a, 0.f));
-        float a2 = b2;
+        for (int q = 0; q < 4; ++q) {
+            const int k = ks * 16 + 4 * lg + q;
 #pragma unroll
-        for (int k = 0; k < NH; ++k) a2 += w2[k] * __shfl(h1, k, LLP_WAVE);
-        const float h2 = round_bf16(fmaxf(a2, 0.f));
-        act[(long long)row * 2 * NH + j] = f32_to_bf16(h1);
-        act[(long long)row * 2 * NH + NH + j] = f32_to_bf16(h2);
+            for (int nt = 0; nt < 4; ++nt) bw2[ks][nt][q] = bfbits(P[OFF_W2 + (nt * 16 + lr) * NH + k]);
+            bw3[ks][q] = lr < NO ? bfbits(P[OFF_W3 + lr * NH + k]) : (short)0;
+        }
+    float b1[4], b2[4];
 #pragma unroll
-        for (int o = 0; o < NO; ++o) {
-            float t = w3[o] * h2;
+    for (int nt = 0; nt < 4; ++nt) {
+        b1[nt] = bfw(P, OFF_B1 + nt * 16 + lr);
+        b2[nt] = bfw(P, OFF_B2 + nt * 16 + lr);
+    }
+    const float b3 = lr < NO ? bfw(P, OFF_B3 + lr) : 0.f;
+    const int ntiles = (B + MT - 1) / MT;
+    for (int tile = blockIdx.x * MW + w; tile < ntiles; tile += gridDim.x * MW) {
+        const long long r0 = (long long)tile * MT;
+        // layer 1: X (16 x 12, padded to 16) times W1^T
+        bf16x4 ax;
 #pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) t += __shfl_xor(t, d, LLP_WAVE);
-            if (j == 0) logits[(long long)row * NO + o] = t + bfw(P, OFF_B3 + o);
+        for (int q = 0; q < 4; ++q) {
+            const int k = 4 * lg + q;
+            ax[q] = (r0 + lr < B && k < NI) ? bfbits(X[(r0 + lr) * NI + k]) : (short)0;
+        }
+        const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const f32x4 d = mma_bf16(ax, bw1[nt], z);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) h[(4 * lg + q) * NH + nt * 16 + lr] = f32_to_bf16(fmaxf(d[q] + b1[nt], 0.f));
+        }
+        // the hidden layers: the tile in LDS turns the accumulator layout into
+        // the operand layout of the next product
+        for (int layer = 0; layer < 2; ++layer) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            bf16x4 ah[4];
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const unsigned short* src = h + lr * NH + ks * 16 + 4 * lg;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) ah[ks][q] = (short)src[q];
+            }
+            // this layer's activations to act (rows of the tile inside the batch)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const long long row = r0 + 4 * lg + q;
+                if (row < B)
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt)
+                        act[row * 2 * NH + layer * NH + nt * 16 + lr] = h[(4 * lg + q) * NH + nt * 16 + lr];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (layer == 0) {
+                // layer 2: H1 W2^T
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    f32x4 d = z;
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) d = mma_bf16(ah[ks], bw2[ks][nt], d);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        h[(4 * lg + q) * NH + nt * 16 + lr] = f32_to_bf16(fmaxf(d[q] + b2[nt], 0.f));
+                }
+            } else {
+                // layer 3: H2 W3^T (5 of 16 columns used)
+                f32x4 d = z;
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) d = mma_bf16(ah[ks], bw3[ks], d);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const long long row = r0 + 4 * lg + q;
+                    if (row < B && lr < NO) logits[row * NO + lr] = d[q] + b3;
+                }
+            }
         }
     }
 }
@@ -113,74 +203,177 @@ __global__ void __launch_bounds__(1024) k_mlp_loss(int B, const float* L, const 
 }
 
 // Backward: grad += d loss / d params (straight through the bf16 rounding).
+// Per tile of 16 rows, with each wave's tiles in LDS as FP32 (rows past the
+// batch are zero and contribute nothing):
+//   dH2 = dL W3 (K = 5, padded to 8), dZ2 = dH2 where H2 > 0;
+//   gW3 += dL^T H2, gW2 += dZ2^T H1;
+//   dH1 = dZ2 W2 (W2 from LDS), dZ1 = dH1 where H1 > 0; gW1 += dZ1^T X;
+//   the biases' gradients are the column sums of dL, dZ2 and dZ1.
+struct BwdWave {
+    float x[MT][16];              // bf16 inputs, columns 12..15 zero
+    float d[MT][8];               // dL, columns 5..7 zero
+    unsigned short h1[MT][NH];    // bf16 bits as stored by the forward pass
+    unsigned short h2[MT][NH];
+    float z[MT][NH];              // dZ2, then dZ1
+};
+struct BwdShared {
+    float w2[NH * NH];  // bf16 W2, row-major [out][in]
+    union {
+        BwdWave wv[MW];
+        float red[NPAR];
+    };
+};
+
+static_assert(sizeof(BwdShared) <= 64 * 1024, "backward LDS within the default per-workgroup limit");
+
 __global__ void __launch_bounds__(MB) k_mlp_backward(int B, const float* P, const float* X,
                                                      const unsigned short* act, const float* dL, float* grad) {
-    __shared__ float red[NPAR];
-    const int j = lane();
-    const int wv = threadIdx.x >> 6;
-    const int wave = blockIdx.x * MW + wv;
-    const int nw = gridDim.x * MW;
-    for (int i = threadIdx.x; i < NPAR; i += MB) red[i] = 0.f;
-    // lane j: column j of W2 (for dh1[j]) and column j of W3 (for dh2[j])
-    float w2c[NH], w3c[NO];
+    extern __shared__ __align__(16) unsigned char smem[];
+    BwdShared& sh = *reinterpret_cast<BwdShared*>(smem);
+    const int l = lane(), w = threadIdx.x >> 6;
+    const int lr = l & 15, lg = l >> 4;
+    for (int i = threadIdx.x; i < NH * NH; i += MB) sh.w2[i] = bfw(P, OFF_W2 + i);
+    // W3 as the B operand of dH2 = dL W3: B[k][j] = W3[k][j], k = ks * 4 + lg (< 5)
+    float bw3[2][4];
 #pragma unroll
-    for (int k = 0; k < NH; ++k) w2c[k] = bfw(P, OFF_W2 + k * NH + j);
+    for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
-    for (int o = 0; o < NO; ++o) w3c[o] = bfw(P, OFF_W3 + o * NH + j);
-    float gW1[NI], gW2[NH], gW3[NO], gb3[NO];
-    float gb1 = 0.f, gb2 = 0.f;
-#pragma unroll
-    for (int k = 0; k < NI; ++k) gW1[k] = 0.f;
-#pragma unroll
-    for (int k = 0; k < NH; ++k) gW2[k] = 0.f;
-#pragma unroll
-    for (int o = 0; o < NO; ++o) gW3[o] = gb3[o] = 0.f;
-    for (int row = wave; row < B; row += nw) {
-        const float h1 = bf16_to_f32(act[(long long)row * 2 * NH + j]);
-        const float h2 = bf16_to_f32(act[(long long)row * 2 * NH + NH + j]);
-        float d[NO];
-#pragma unroll
-        for (int o = 0; o < NO; ++o) d[o] = dL[(long long)row * NO + o];
-        // layer 3: logits = W3 h2 + b3
-        float dh2 = 0.f;
-#pragma unroll
-        for (int o = 0; o < NO; ++o) {
-            gW3[o] += d[o] * h2;
-            gb3[o] += d[o];
-            dh2 += w3c[o] * d[o];
+        for (int nt = 0; nt < 4; ++nt) {
+            const int k = ks * 4 + lg;
+            bw3[ks][nt] = k < NO ? bfw(P, OFF_W3 + k * NH + nt * 16 + lr) : 0.f;
         }
-        const float dz2 = h2 > 0.f ? dh2 : 0.f;
-        gb2 += dz2;
-        // lane j holds row j of W2's gradient: dz2[j] * h1[k]
+    const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    f32x4 g2[4][4], g1[4], g3[4];
 #pragma unroll
-        for (int k = 0; k < NH; ++k) gW2[k] += dz2 * __shfl(h1, k, LLP_WAVE);
-        // dh1[j] = sum_k W2[k][j] dz2[k]
-        float dh1 = 0.f;
+    for (int a = 0; a < 4; ++a) {
+        g1[a] = z;
+        g3[a] = z;
 #pragma unroll
-        for (int k = 0; k < NH; ++k) dh1 += w2c[k] * __shfl(dz2, k, LLP_WAVE);
-        const float dz1 = h1 > 0.f ? dh1 : 0.f;
-        gb1 += dz1;
-        const float* x = X + (long long)row * NI;
-#pragma unroll
-        for (int k = 0; k < NI; ++k) gW1[k] += dz1 * round_bf16(x[k]);
+        for (int b = 0; b < 4; ++b) g2[a][b] = z;
     }
+    float gb1 = 0.f, gb2 = 0.f, gb3 = 0.f;   // lane l: column l (gb3: l < 5)
     __syncthreads();
-    // reduce the workgroup's waves in LDS
+    BwdWave& t = sh.wv[w];
+    const int ntiles = (B + MT - 1) / MT;
+    for (int tile = blockIdx.x * MW + w; tile < ntiles; tile += gridDim.x * MW) {
+        const long long r0 = (long long)tile * MT;
+        // the tile's rows into LDS: 64 lanes over 16 rows
+        for (int i = l; i < MT * NH; i += LLP_WAVE) {
+            const int row = i / NH, c = i % NH;
+            const bool in = r0 + row < B;
+            t.h1[row][c] = in ? act[(r0 + row) * 2 * NH + c] : (unsigned short)0;
+            t.h2[row][c] = in ? act[(r0 + row) * 2 * NH + NH + c] : (unsigned short)0;
+        }
+        for (int i = l; i < MT * 16; i += LLP_WAVE) {
+            const int row = i / 16, c = i % 16;
+            t.x[row][c] = (r0 + row < B && c < NI) ? round_bf16(X[(r0 + row) * NI + c]) : 0.f;
+        }
+        for (int i = l; i < MT * 8; i += LLP_WAVE) {
+            const int row = i / 8, c = i % 8;
+            t.d[row][c] = (r0 + row < B && c < NO) ? dL[(r0 + row) * NO + c] : 0.f;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // dZ2 = (dL W3) where H2 > 0
 #pragma unroll
-    for (int k = 0; k < NI; ++k) atomicAdd(&red[OFF_W1 + j * NI + k], gW1[k]);
-    atomicAdd(&red[OFF_B1 + j], gb1);
+        for (int nt = 0; nt < 4; ++nt) {
+            f32x4 d = z;
 #pragma unroll
-    for (int k = 0; k < NH; ++k) atomicAdd(&red[OFF_W2 + j * NH + k], gW2[k]);
-    atomicAdd(&red[OFF_B2 + j], gb2);
+            for (int ks = 0; ks < 2; ++ks) d = mma_f32(t.d[lr][ks * 4 + lg], bw3[ks][nt], d);
 #pragma unroll
-    for (int o = 0; o < NO; ++o) atomicAdd(&red[OFF_W3 + o * NH + j], gW3[o]);
-    if (j == 0) {
+            for (int q = 0; q < 4; ++q) {
+                const int row = 4 * lg + q, c = nt * 16 + lr;
+                t.z[row][c] = bf16_to_f32(t.h2[row][c]) > 0.f ? d[q] : 0.f;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // gW3 += dL^T H2 (rows of the output: 5 of 16) and gW2 += dZ2^T H1, K = the tile's rows
 #pragma unroll
-        for (int o = 0; o < NO; ++o) atomicAdd(&red[OFF_B3 + o], gb3[o]);
+        for (int ks = 0; ks < 4; ++ks) {
+            const int k = ks * 4 + lg;
+            const float a3 = lr < 8 ? t.d[k][lr] : 0.f;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                g3[nt] = mma_f32(a3, bf16_to_f32(t.h2[k][nt * 16 + lr]), g3[nt]);
+                const float b = bf16_to_f32(t.h1[k][nt * 16 + lr]);
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) g2[mt][nt] = mma_f32(t.z[k][mt * 16 + lr], b, g2[mt][nt]);
+            }
+        }
+        // bias gradients: column sums
+        {
+            float s2 = 0.f;
+            for (int row = 0; row < MT; ++row) s2 += t.z[row][l];
+            gb2 += s2;
+        }
+        if (l < NO) {
+            float s3 = 0.f;
+            for (int row = 0; row < MT; ++row) s3 += t.d[row][l];
+            gb3 += s3;
+        }
+        // dZ1 = (dZ2 W2) where H1 > 0, into the dZ2 tile once every lane has read it
+        f32x4 dh[4] = {z, z, z, z};
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+            const float a = t.z[lr][ks * 4 + lg];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) dh[nt] = mma_f32(a, sh.w2[(ks * 4 + lg) * NH + nt * 16 + lr], dh[nt]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = 4 * lg + q, c = nt * 16 + lr;
+                t.z[row][c] = bf16_to_f32(t.h1[row][c]) > 0.f ? dh[nt][q] : 0.f;
+            }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // gW1 += dZ1^T X
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int k = ks * 4 + lg;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) g1[mt] = mma_f32(t.z[k][mt * 16 + lr], t.x[k][lr], g1[mt]);
+        }
+        {
+            float s1 = 0.f;
+            for (int row = 0; row < MT; ++row) s1 += t.z[row][l];
+            gb1 += s1;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    // reduce the workgroup's waves in LDS (the tiles' space becomes the sums)
+    __syncthreads();
+    for (int i = threadIdx.x; i < NPAR; i += MB) sh.red[i] = 0.f;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = 4 * lg + q;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) atomicAdd(&sh.red[OFF_W2 + (mt * 16 + r) * NH + nt * 16 + lr], g2[mt][nt][q]);
+            if (r < NO) atomicAdd(&sh.red[OFF_W3 + r * NH + nt * 16 + lr], g3[nt][q]);
+        }
+        if (lr < NI)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) atomicAdd(&sh.red[OFF_W1 + (mt * 16 + r) * NI + lr], g1[mt][q]);
+    }
+    atomicAdd(&sh.red[OFF_B1 + l], gb1);
+    atomicAdd(&sh.red[OFF_B2 + l], gb2);
+    if (l < NO) atomicAdd(&sh.red[OFF_B3 + l], gb3);
     __syncthreads();
     for (int i = threadIdx.x; i < NPAR; i += MB)
-        if (red[i] != 0.f) atomicAdd(&grad[i], red[i]);
+        if (sh.red[i] != 0.f) atomicAdd(&grad[i], sh.red[i]);
 }
 
 __global__ void k_mlp_adam(const float* g, float* p, float* m1, float* m2, int step, float lr) {
@@ -219,8 +412,9 @@ __global__ void k_trace_features(long long rounds, const llp_trace_rec* tr, int 
     }
 }
 
+// one wave per tile of MT rows
 static int mlp_grid(int B) {
-    int g = (B + MW - 1) / MW;
+    int g = (B + MT * MW - 1) / (MT * MW);
     int cap = device_info().cus * 4;
     if (g > cap) g = cap;
     return g < 1 ? 1 : g;
@@ -249,8 +443,8 @@ int llp_mlp_backward(int32_t B, const float* params, const float* x, const uint1
     if (B < 0 || !params || !grad || (B > 0 && (!x || !act || !dlogits)))
         return llp::fail(LLP_E_ARG, "bad backward arguments");
     if (B == 0) return LLP_OK;
-    hipLaunchKernelGGL(llp::k_mlp_backward, dim3(llp::mlp_grid(B)), dim3(llp::MB), 0, (hipStream_t)stream, B,
-                       params, x, act, dlogits, grad);
+    hipLaunchKernelGGL(llp::k_mlp_backward, dim3(llp::mlp_grid(B)), dim3(llp::MB), sizeof(llp::BwdShared),
+                       (hipStream_t)stream, B, params, x, act, dlogits, grad);
     return llp::hip_check(hipGetLastError(), "k_mlp_backward");
 }
 
