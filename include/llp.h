@@ -300,16 +300,41 @@ int llp_solve_batch_graph(int32_t count, const llp_instance* desc, const int32_t
    Times each candidate (threads per workgroup in {256, 512, 1024} x
    instances per queue claim in {1, 2, 4, 8}) of the batch kernel on the given
    batch (median of 3 timed launches after one warm-up) and records the
-   fastest under the current device; llp_solve_batch uses it when
-   opts->block and opts->chunk are 0.  Writes one "block chunk ms" line per
+   fastest for the current device and the batch's size class (see below);
+   llp_solve_batch uses it when opts->block and opts->chunk are 0.  Writes one "block chunk ms" line per
    candidate to report (nullable, host) as text, up to report_bytes.
    Outputs of the batch are left as computed by the last candidate. */
 int llp_autotune_batch(int32_t count, const llp_instance* desc, const int32_t* pool, int64_t pool_words,
                        int32_t* out_pool, int64_t out_words, char* report, size_t report_bytes,
                        const llp_opts* opts);
-/* The recorded choice for kind (LLP_KIND_BATCH) on the current device;
-   LLP_E_ARG if none has been recorded. */
+/* Times the graph sweep at 1, 2, 3 and 4 workgroups per CU (opts->chunk) on
+   this graph for kind LLP_KIND_SSSP or LLP_KIND_BFS from source, with the
+   schedule and flags of opts (median of 3 timed solves after one warm-up)
+   and records the fastest for the kind and the size class of g->m; solves
+   with opts->chunk = 0 use it.  out [device, n] receives the fixpoint, which
+   the shape does not change.  One "chunk ms" line per candidate goes to report
+   (nullable, host).  A caller-provided workspace must hold
+   llp_workspace_bytes(kind, n, m, opts with chunk 0). */
+int llp_autotune_graph(const llp_graph* g, int32_t source, int32_t kind, int32_t* out, char* report,
+                       size_t report_bytes, const llp_opts* opts);
+/* The most recently recorded choice for kind (LLP_KIND_BATCH: block and
+   chunk; LLP_KIND_SSSP / LLP_KIND_BFS: block 0 and the workgroups per CU) on
+   the current device; LLP_E_ARG if none has been recorded. */
 int llp_autotune_get(int kind, int32_t* block, int32_t* chunk);
+/* Records are kept per (GPU architecture, CU count, kind, size class), the
+   size class being floor(log2(size)) with size the instance count of a batch
+   or the arc count m of a graph.  A solve that leaves its shape to the
+   library takes the record of its class on the current device, else that of
+   the nearest class of the same kind (the larger on a tie), else the default.
+   llp_autotune_lookup returns that choice for a size (LLP_E_ARG if none).
+   llp_autotune_save writes every record, of every architecture, to a JSON
+   file (host path; written to path.tmp, then renamed); llp_autotune_load adds
+   the records of such a file (LLP_E_INPUT if it is malformed or out of range,
+   in which case none is taken) and stores their number in *loaded (nullable).
+   Neither needs a GPU.  llp_shutdown forgets every record. */
+int llp_autotune_lookup(int32_t kind, int64_t size, int32_t* block, int32_t* chunk);
+int llp_autotune_save(const char* path);
+int llp_autotune_load(const char* path, int32_t* loaded);
 
 /* ---------------------------------------------------------------- learned scheduler
    Network: 12 round features -> 64 -> 64 -> 5 outputs (ReLU hidden layers),

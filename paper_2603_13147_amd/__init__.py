@@ -124,6 +124,10 @@ def lib():
         ("llp_solve_batch_graph", [i32, vp, vp, i64, vp, i64, vp, po]),
         ("llp_autotune_batch", [i32, vp, vp, i64, vp, i64, ctypes.c_char_p, sz, po]),
         ("llp_autotune_get", [ctypes.c_int, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        ("llp_autotune_graph", [ctypes.POINTER(Graph), i32, i32, vp, ctypes.c_char_p, sz, po]),
+        ("llp_autotune_lookup", [i32, i64, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        ("llp_autotune_save", [ctypes.c_char_p]),
+        ("llp_autotune_load", [ctypes.c_char_p, ctypes.POINTER(i32)]),
         ("llp_mlp_forward", [i32, vp, vp, vp, vp, vp]),
         ("llp_mlp_loss", [i32, vp, vp, vp, vp, vp]),
         ("llp_mlp_backward", [i32, vp, vp, vp, vp, vp, vp]),
@@ -433,9 +437,47 @@ class Batch:
 
 
 def autotune_get(kind=KIND_BATCH):
+    """The most recently recorded (block, chunk) for kind on this device."""
     b, c = ctypes.c_int32(0), ctypes.c_int32(0)
     _check(lib().llp_autotune_get(kind, ctypes.byref(b), ctypes.byref(c)))
     return b.value, c.value
+
+
+def autotune_graph(dg, source, kind=KIND_SSSP, out=None, ws=None, **kw):
+    """Time the sweep at 1..4 workgroups per CU on this graph and record the
+    fastest for (kind, size class of m); returns ([(chunk, ms)], out)."""
+    torch = _torch()
+    if ws is None:
+        ws = workspace(kind, dg.n, dg.m, 0)
+    o = make_opts(workspace=ws, **kw)
+    out = _out(out, (dg.n,), torch.int32, "out")
+    g = dg.cstruct()
+    buf = ctypes.create_string_buffer(1024)
+    _check(lib().llp_autotune_graph(ctypes.byref(g), int(source), kind, _ptr(out), buf, 1024, ctypes.byref(o)))
+    rows = []
+    for line in buf.value.decode().splitlines():
+        c, ms = line.split()
+        rows.append((int(c), float(ms)))
+    return rows, out
+
+
+def autotune_lookup(kind, size):
+    """(block, chunk) a solve of kind and size would take from the records."""
+    b, c = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().llp_autotune_lookup(kind, int(size), ctypes.byref(b), ctypes.byref(c)))
+    return b.value, c.value
+
+
+def autotune_save(path):
+    """Write every autotuner record to a JSON cache file."""
+    _check(lib().llp_autotune_save(os.fsencode(path)))
+
+
+def autotune_load(path):
+    """Add the records of a JSON cache file; returns how many it held."""
+    n = ctypes.c_int32(0)
+    _check(lib().llp_autotune_load(os.fsencode(path), ctypes.byref(n)))
+    return n.value
 
 
 # ---------------------------------------------------------------- transitive closure / reduction

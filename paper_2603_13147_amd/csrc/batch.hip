@@ -478,12 +478,7 @@ int solve_knapsack(int32_t items, int32_t W, const int32_t* wt, const int32_t* v
 }
 
 // ---------------------------------------------------------------- batch
-struct TuneKey {
-    int device;
-    bool operator<(const TuneKey& o) const { return device < o.device; }
-};
 static std::mutex g_bmu;
-static std::map<int, std::pair<int, int>> g_tuned;   // device -> (block, chunk)
 
 struct BatchPlan {
     int block, chunk, ch;
@@ -515,11 +510,11 @@ static int batch_plan(int32_t count, const llp_instance* desc, const llp_opts& o
     if (h.max_n > SS_MAX_N) return fail(LLP_E_ARG, "an SSSP instance has n = %d > %d", h.max_n, SS_MAX_N);
     int block = o.block, chunk = o.chunk;
     if (block <= 0 || chunk <= 0) {
-        std::lock_guard<std::mutex> lk(g_bmu);
-        auto it = g_tuned.find(device_info().device);
-        if (it != g_tuned.end()) {
-            if (block <= 0) block = it->second.first;
-            if (chunk <= 0) chunk = it->second.second;
+        // the autotuner's record for this batch's size class (or the nearest)
+        int tb = 0, tc = 0;
+        if (tune_lookup(LLP_KIND_BATCH, count, &tb, &tc)) {
+            if (block <= 0) block = tb;
+            if (chunk <= 0) chunk = tc;
         }
     }
     if (block <= 0) block = 512;   // the autotuner's usual choice on the mixed batch
@@ -799,7 +794,7 @@ void batch_release() {
         if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
     }
     g_graphs.clear();
-    g_tuned.clear();
+    tune_clear();
 }
 
 // ---------------------------------------------------------------- autotuner
@@ -858,10 +853,7 @@ int autotune_batch(int32_t count, const llp_instance* desc, const int32_t* pool,
     (void)hipEventDestroy(e1);
     if (s) return s;
     if (!best_b) return fail(LLP_E_ARG, "no launch shape can hold this batch");
-    {
-        std::lock_guard<std::mutex> lk(g_bmu);
-        g_tuned[device_info().device] = {best_b, best_c};
-    }
+    tune_record(LLP_KIND_BATCH, count, best_b, best_c);
     if (report && report_bytes) {
         size_t k = rep.size() < report_bytes - 1 ? rep.size() : report_bytes - 1;
         memcpy(report, rep.data(), k);
@@ -871,12 +863,12 @@ int autotune_batch(int32_t count, const llp_instance* desc, const int32_t* pool,
 }
 
 int autotune_get(int kind, int32_t* block, int32_t* chunk) {
-    if (kind != LLP_KIND_BATCH) return fail(LLP_E_ARG, "only LLP_KIND_BATCH is tuned");
-    std::lock_guard<std::mutex> lk(g_bmu);
-    auto it = g_tuned.find(device_info().device);
-    if (it == g_tuned.end()) return fail(LLP_E_ARG, "no tuned shape recorded on this device");
-    if (block) *block = it->second.first;
-    if (chunk) *chunk = it->second.second;
+    if (kind != LLP_KIND_BATCH && kind != LLP_KIND_SSSP && kind != LLP_KIND_BFS)
+        return fail(LLP_E_ARG, "only LLP_KIND_BATCH, LLP_KIND_SSSP and LLP_KIND_BFS are tuned");
+    int b = 0, c = 0;
+    if (!tune_last(kind, &b, &c)) return fail(LLP_E_ARG, "no tuned shape recorded on this device");
+    if (block) *block = b;
+    if (chunk) *chunk = c;
     return LLP_OK;
 }
 

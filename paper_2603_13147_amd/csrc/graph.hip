@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "llp_host.h"
@@ -1513,6 +1514,10 @@ struct GraphLayout {
 // per_cu: workgroups (= list segments) per CU, opts->chunk for graph solves;
 // the default 2 keeps every workgroup of a phase kernel resident at once.
 static int graph_wgs_per_cu(int chunk) { return chunk > 0 ? (chunk > 8 ? 8 : chunk) : 2; }
+// workgroups per CU the autotuner tries (llp_autotune_graph); a solve that
+// leaves the choice to the library (chunk 0) takes the record of its size
+// class, so workspaces sized for chunk 0 hold every candidate
+constexpr int GRAPH_TUNE_MAX = 4;
 
 static GraphLayout graph_layout(int64_t m, int per_cu) {
     const DeviceInfo& d = device_info();
@@ -1558,7 +1563,10 @@ static size_t graph_ws(int64_t n, int64_t m, int per_cu, GArgs* a, char* base, s
 }
 
 size_t graph_workspace_bytes(int64_t n, int64_t m, int chunk) {
-    return graph_ws(n, m, graph_wgs_per_cu(chunk), nullptr, nullptr, 0);
+    if (chunk > 0) return graph_ws(n, m, graph_wgs_per_cu(chunk), nullptr, nullptr, 0);
+    size_t b = 0;
+    for (int c = 1; c <= GRAPH_TUNE_MAX; ++c) b = std::max(b, graph_ws(n, m, c, nullptr, nullptr, 0));
+    return b;
 }
 
 __global__ void k_fill_i8(signed char* p, long long n, signed char v) {
@@ -1653,7 +1661,11 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
     if (s) return s;
     hybrid_params(jobs_dur ? LLP_KIND_JOBS : (bfs ? LLP_KIND_BFS : LLP_KIND_SSSP), g->n, g->m, can_push, &a.sp);
 
-    const int per_cu = graph_wgs_per_cu(o.chunk);
+    int per_cu = graph_wgs_per_cu(o.chunk);
+    if (o.chunk <= 0 && !jobs_dur) {
+        int tb = 0, tc = 0;
+        if (tune_lookup(bfs ? LLP_KIND_BFS : LLP_KIND_SSSP, g->m, &tb, &tc)) per_cu = std::min(std::max(tc, 1), GRAPH_TUNE_MAX);
+    }
     size_t need = graph_ws(g->n, g->m, per_cu, nullptr, nullptr, 0);
     void* ws = nullptr;
     s = get_workspace(o, need, &ws);
@@ -1862,9 +1874,68 @@ int solve_jobs_pull(int32_t n, const int32_t* pred_ptr, const int32_t* pred_idx,
     return solve_graph_core(&g, 0, start, opts, false, dur);
 }
 
+// Time the sweep at each workgroup count per CU (1 .. GRAPH_TUNE_MAX) on this
+// graph with the caller's schedule: median of 3 solves after a warm-up, HIP
+// events around each (every solve ends with its readback); record the fastest
+// for (kind, size class of m).
+int autotune_graph(const llp_graph* g, int32_t source, int32_t kind, int32_t* out, char* report,
+                   size_t report_bytes, const llp_opts* opts) {
+    if (kind != LLP_KIND_SSSP && kind != LLP_KIND_BFS) return fail(LLP_E_ARG, "kind must be LLP_KIND_SSSP or LLP_KIND_BFS");
+    if (!g) return fail(LLP_E_ARG, "graph is NULL");
+    llp_opts o = opts_or_default(opts);
+    o.flags &= ~(LLP_ASYNC | LLP_TIMING | LLP_TRACE);
+    o.stats = nullptr;
+    hipStream_t st = (hipStream_t)o.stream;
+    hipEvent_t e0, e1;
+    LLP_HIP(hipEventCreate(&e0));
+    LLP_HIP(hipEventCreate(&e1));
+    std::string rep;
+    float best_ms = 1e30f;
+    int best_c = 0, s = LLP_OK;
+    for (int c = 1; c <= GRAPH_TUNE_MAX && s == LLP_OK; ++c) {
+        llp_opts oc = o;
+        oc.chunk = c;
+        std::vector<float> ts;
+        for (int r = 0; r < 4 && s == LLP_OK; ++r) {
+            if (hipEventRecord(e0, st) != hipSuccess) s = fail(LLP_E_HIP, "hipEventRecord failed");
+            if (s == LLP_OK) s = solve_graph(g, source, out, &oc, kind == LLP_KIND_BFS);
+            if (s == LLP_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                s = fail(LLP_E_HIP, "timing events failed");
+            float ms = 0.f;
+            if (s == LLP_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) s = fail(LLP_E_HIP, "hipEventElapsedTime failed");
+            if (s == LLP_OK && r > 0) ts.push_back(ms);
+        }
+        if (s) break;
+        std::sort(ts.begin(), ts.end());
+        const float med = ts[ts.size() / 2];
+        char line[64];
+        snprintf(line, sizeof(line), "%d %.4f\n", c, med);
+        rep += line;
+        if (med < best_ms) {
+            best_ms = med;
+            best_c = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s) return s;
+    tune_record(kind, g->m, 0, best_c);
+    if (report && report_bytes) {
+        const size_t k = rep.size() < report_bytes - 1 ? rep.size() : report_bytes - 1;
+        memcpy(report, rep.data(), k);
+        report[k] = 0;
+    }
+    return LLP_OK;
+}
+
 }  // namespace llp
 
 extern "C" {
+
+int llp_autotune_graph(const llp_graph* g, int32_t source, int32_t kind, int32_t* out, char* report,
+                       size_t report_bytes, const llp_opts* opts) {
+    return llp::autotune_graph(g, source, kind, out, report, report_bytes, opts);
+}
 
 int llp_solve_sssp(const llp_graph* g, int32_t source, int32_t* dist, const llp_opts* opts) {
     return llp::solve_graph(g, source, dist, opts, false);

@@ -34,6 +34,14 @@ struct DeviceInfo {
 };
 const DeviceInfo& device_info();
 
+// Autotuner records (tune.cpp), per (architecture, CU count, kind, size
+// class = floor(log2(size))) of the current device.
+int size_class(long long size);
+void tune_record(int kind, long long size, int block, int chunk);
+bool tune_lookup(int kind, long long size, int* block, int* chunk);   // own class, else the nearest
+bool tune_last(int kind, int* block, int* chunk);                      // the most recent record
+void tune_clear();
+
 // copy of opts with defaults filled in
 llp_opts opts_or_default(const llp_opts* o);
 

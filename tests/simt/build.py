@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_2603_13147_amd", "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT, "libllp_simt.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("graph.hip", "jobs.hip", "llp_host.cpp", "sched_host.cpp", "abi.cpp")] + \
+SOURCES = [os.path.join(CSRC, f) for f in ("graph.hip", "jobs.hip", "llp_host.cpp", "sched_host.cpp", "abi.cpp", "tune.cpp")] + \
           [os.path.join(HERE, f) for f in ("simt.cpp", "stubs.cpp")]
 
 
