@@ -26,6 +26,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "llp_host.h"
@@ -59,6 +60,7 @@ struct GCtrl {
     int stop[2];        // step launch k returns at once when stop[k & 1] is set (see k_graph_step)
     unsigned tail_bar;  // barrier counter of a tail launch (cleared before each)
     int tail_rounds;    // rounds run by tail launches
+    int end_k;          // the step launch that found the end
 };
 
 struct GArgs {
@@ -1021,6 +1023,7 @@ __device__ int pre_phase(const GArgs& a, int r, int k, GShared& sh) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             a.ctrl->done = 1;
             a.ctrl->last_round = r - 1;
+            a.ctrl->end_k = k;
             st_relaxed(&a.ctrl->stop[(k + 1) & 1], 1);
         }
         // the sweep has ended: every workgroup sees it, and no other launch
@@ -1617,6 +1620,16 @@ static int launch_grid_1d(int64_t work) {
     return (int)(g < cap ? g : cap);
 }
 
+// The step launches the last sweep of the same graph arrays, kind and
+// schedule needed (sweeps that ended in step launches only).  The next such
+// sweep sizes its first batch from it, never above the default, so a
+// repeated solve enqueues few launches past its end; a sweep that needs more
+// pays one more readback.  Outputs do not depend on it.
+using SweepKey = std::tuple<const void*, const void*, int, long long, int, unsigned, unsigned, int>;
+static std::mutex g_hmu;
+static std::map<SweepKey, int> g_hist;
+constexpr int FIRST_BATCH = 16;
+
 // jobs != nullptr: the pull form of job scheduling (in-CSR = predecessor
 // lists, out-CSR = successor lists, per-job durations), otherwise SSSP / BFS.
 static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, const llp_opts* opts, bool bfs,
@@ -1693,11 +1706,19 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
     a.max_rounds = max_rounds;
     GCtrl h;
     memset(&h, 0, sizeof(h));
-    // step launches: at most two per round; the first batch (16) covers a
-    // typical R-MAT sweep, then the batch doubles up to 64
+    // step launches: at most two per round; the first batch (16, or what the
+    // last sweep of this graph and schedule needed) covers a typical R-MAT
+    // sweep, then the batch doubles up to 64
     const int64_t max_launches = 2 * max_rounds + 4;
     int64_t k = 0;
-    int batch = 16;
+    const SweepKey hkey(g->in_ptr, g->out_ptr, g->n, (long long)g->m, jobs_dur ? 2 : (bfs ? 1 : 0), o.sched,
+                        o.flags & (LLP_PUSH | LLP_DENSE), o.delta);
+    int batch = FIRST_BATCH;
+    {
+        std::lock_guard<std::mutex> lk(g_hmu);
+        auto it = g_hist.find(hkey);
+        if (it != g_hist.end()) batch = std::max(2, std::min(FIRST_BATCH, it->second + 1));
+    }
     int status = LLP_OK;
     bool finished = false;           // overflow check and decode done inside the loop
     std::vector<hipEvent_t> evs;     // LLP_TIMING: one pair around each step launch
@@ -1794,6 +1815,11 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
         if (timing) LLP_HIP(hipEventRecord(ev1, st));
         s = readback(st, a.ctrl, &h, sizeof(h));
         if (s) return s;
+    }
+    if (h.done && !h.over && h.status == 0 && tail_launches == 0 && h.end_k >= 0) {
+        std::lock_guard<std::mutex> lk(g_hmu);
+        if (g_hist.size() >= 256) g_hist.clear();
+        g_hist[hkey] = h.end_k + 1;
     }
     if (o.stats) {
         memset(o.stats, 0, sizeof(*o.stats));
