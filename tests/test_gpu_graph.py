@@ -274,6 +274,26 @@ def test_chain_rounds(kind):
         assert st.eval_launches == 0 and st.pre_launches <= R
 
 
+def test_first_batch_from_the_last_sweep():
+    """The first batch of step launches is sized from the last sweep of the
+    same graph and schedule: a 6-vertex chain solved from its head (6 pull
+    rounds) and then a 300-vertex chain of the same graph from its head (300
+    rounds, far past that first batch, so more readbacks follow), then the
+    short one again; every fixpoint is the oracle's."""
+    short, long_ = 6, 300
+    src = np.concatenate([np.arange(short - 1), short + np.arange(long_ - 1)]).astype(np.int32)
+    dst = (src + 1).astype(np.int32)
+    w = llpgen.uniform_ints(src.shape[0], 1, 9, seed=12).astype(np.int32)
+    g = llpgen.EdgeList(short + long_, src, dst, w)
+    _, dg = dev_graph(g)
+    for s in (0, short, 0, short):
+        for fn, want in ((llp.sssp, oracle.sssp(g.n, g.src, g.dst, g.w, s)), (llp.bfs, oracle.bfs(g.n, g.src, g.dst, s))):
+            st = llp.Stats()
+            got = run(fn, dg, s, stats=st, sched=llp.SCHED_PLAIN)
+            assert np.array_equal(got, want), (s, fn.__name__)
+            assert st.rounds == (short - 1 if s == 0 else long_ - 1)
+
+
 DELTA_SCHEDS = [dict(sched=llp.SCHED_FIXED, delta=d) for d in (1, 16, 64, 255, 4000)] + [
     dict(sched=llp.SCHED_FIXED, flags=llp.PUSH, delta=32),
     dict(sched=llp.SCHED_RANDOM, seed=3), dict(sched=llp.SCHED_RANDOM, seed=4),
