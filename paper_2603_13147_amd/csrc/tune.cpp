@@ -64,7 +64,7 @@ int kind_of(const std::string& s) {
 bool valid(int kind, int cls, int cus, int block, int chunk) {
     if (!kind_name(kind) || cls < 0 || cls > 62 || cus < 1 || chunk < 1 || chunk > 64) return false;
     if (kind == LLP_KIND_BATCH) return block >= 64 && block <= 1024 && block % 64 == 0;
-    return block == 0 && chunk <= 8;
+    return block == 0 && chunk <= 4;   // the graph tuner's candidates: 1 to 4 workgroups per CU
 }
 
 // the text of field key in the object [b, e): a quoted string's contents or a number

@@ -77,7 +77,7 @@ def test_shutdown_forgets_records(lib, tmp_path):
 
 @pytest.mark.parametrize("bad", [
     [dict(ENTRIES[0], block=100)],                       # batch block not a multiple of 64
-    [dict(ENTRIES[1], chunk=9)],                         # graph workgroups per CU above 8
+    [dict(ENTRIES[1], chunk=5)],                         # graph workgroups per CU above the tuner's 4
     [dict(ENTRIES[1], block=256)],                       # graph records carry no block
     [dict(ENTRIES[0], kind="knapsack")],                 # kind the tuner does not record
     [dict(ENTRIES[0], size_class=63)],
