@@ -166,13 +166,13 @@ int tune_save(const char* path) {
         std::lock_guard<std::mutex> lk(g_tmu);
         bool first = true;
         for (const auto& kv : g_recs) {
-            char line[256];
-            snprintf(line, sizeof(line),
-                     "%s\n {\"arch\": \"%s\", \"cus\": %d, \"kind\": \"%s\", \"size_class\": %d, \"block\": %d, "
-                     "\"chunk\": %d}",
-                     first ? "" : ",", std::get<0>(kv.first).c_str(), std::get<1>(kv.first),
-                     kind_name(std::get<2>(kv.first)), std::get<3>(kv.first), kv.second.block, kv.second.chunk);
-            text += line;
+            text += first ? "\n {\"arch\": \"" : ",\n {\"arch\": \"";
+            text += std::get<0>(kv.first);
+            text += "\", \"cus\": " + std::to_string(std::get<1>(kv.first));
+            text += ", \"kind\": \"" + std::string(kind_name(std::get<2>(kv.first)));
+            text += "\", \"size_class\": " + std::to_string(std::get<3>(kv.first));
+            text += ", \"block\": " + std::to_string(kv.second.block);
+            text += ", \"chunk\": " + std::to_string(kv.second.chunk) + "}";
             first = false;
         }
     }
@@ -221,7 +221,11 @@ int tune_load(const char* path, int* loaded) {
             !int_field(s, b, e, "chunk", &chunk))
             return fail(LLP_E_INPUT, "%s: entry at byte %zu lacks a field", path, b);
         const int kd = kind_of(kind);
-        if (arch.empty() || !valid(kd, cls, cus, block, chunk))
+        bool name_ok = !arch.empty() && arch.size() <= 64;
+        for (char ch : arch)
+            name_ok = name_ok && ((ch >= 'a' && ch <= 'z') || (ch >= 'A' && ch <= 'Z') || (ch >= '0' && ch <= '9') ||
+                                  ch == '_' || ch == '-' || ch == '.' || ch == '+');
+        if (!name_ok || !valid(kd, cls, cus, block, chunk))
             return fail(LLP_E_INPUT, "%s: entry at byte %zu is out of range", path, b);
         add[Key(arch, cus, kd, cls)] = Rec{block, chunk, 0};
     }

@@ -83,6 +83,8 @@ def test_shutdown_forgets_records(lib, tmp_path):
     [dict(ENTRIES[0], size_class=63)],
     [{k: v for k, v in ENTRIES[0].items() if k != "cus"}],
     [ENTRIES[0], dict(ENTRIES[1], cus=0)],               # one bad entry rejects the file
+    [dict(ENTRIES[0], arch="gfx950 x")],                 # architecture names are plain tokens
+    [dict(ENTRIES[0], arch="g" * 65)],
 ])
 def test_malformed_cache_is_rejected_whole(lib, tmp_path, bad):
     src, out = tmp_path / "bad.json", tmp_path / "b.json"
