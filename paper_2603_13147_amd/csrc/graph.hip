@@ -89,15 +89,22 @@ struct GArgs {
     long long plog_cap;
     long long max_rounds;
     SchedParams sp;
+    int dbase_known;       // > 0: the delta base width of these weights, sampled by an earlier solve
 };
 
 __device__ __forceinline__ ListRef cl_of(const GArgs& a, int r) { return (r & 1) ? a.cl1 : a.cl0; }
 
 // --------------------------------------------------------------- init
+// Workgroup 0 writes the control block, the list words and CL[0], after its
+// sample of the arcs' weights (a chain of random loads); the other workgroups
+// clear the state meanwhile, so the sample is off the launch's critical path.
+// A launch of one workgroup does both.
 __global__ void k_graph_init(GArgs a, const int* warm) {
-    const long long tid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const long long nt = (long long)gridDim.x * blockDim.x;
-    for (long long v = tid; v < a.n; v += nt) {
+    const bool clears = gridDim.x == 1 || blockIdx.x > 0;
+    const long long nb = gridDim.x > 1 ? gridDim.x - 1 : 1;
+    const long long tid = (gridDim.x > 1 ? blockIdx.x - 1 : 0) * (long long)blockDim.x + threadIdx.x;
+    const long long nt = nb * blockDim.x;
+    for (long long v = tid; clears && v < a.n; v += nt) {
         int g = 0;
         if (a.jobs) {
             g = warm && warm[v] > 0 ? warm[v] : 0;
@@ -112,20 +119,21 @@ __global__ void k_graph_init(GArgs a, const int* warm) {
         a.stamp[v] = 0;
         a.cstamp[v] = 0;
     }
-    for (long long s = tid; s < a.nseg; s += nt) {
-        a.cl0.seg[s] = 0ull;
-        a.cl1.seg[s] = 0ull;
-        a.wl.seg[s] = 0ull;
-        a.cl0.segmin[s] = LLP_INF;
-        a.cl1.segmin[s] = LLP_INF;
-    }
     if (blockIdx.x == 0) {
+        // the list words (segment 0's is seeded below, after the barrier)
+        for (int s = threadIdx.x; s < a.nseg; s += blockDim.x) {
+            a.cl0.seg[s] = 0ull;
+            a.cl1.seg[s] = 0ull;
+            a.wl.seg[s] = 0ull;
+            a.cl0.segmin[s] = LLP_INF;
+            a.cl1.segmin[s] = LLP_INF;
+        }
         // delta base width: 2^floor(log2 of the mean weight of a stride sample of
         // the in-arcs) (1 for unit weights)
         __shared__ long long wsum[4];
         long long sum = 0;
         int cnt = 0;
-        if (!a.unit_w && !a.jobs && a.in_w && a.m > 0) {
+        if (!a.unit_w && !a.jobs && a.in_w && a.m > 0 && a.dbase_known <= 0) {
             // sample i of 4096 is arc i m / 4096; the 16 loads of a thread
             // are issued before any is summed (the launch has 256 threads)
             int wv[16];
@@ -144,7 +152,7 @@ __global__ void k_graph_init(GArgs a, const int* warm) {
         if (threadIdx.x == 0) {
             long long t = 0;
             for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += wsum[k];
-            int base = 1;
+            int base = a.dbase_known > 0 ? a.dbase_known : 1;
             if (cnt) {
                 long long mean = t / cnt;
                 while ((long long)base * 2 <= mean && base < (1 << 29)) base *= 2;
@@ -1628,6 +1636,11 @@ static int launch_grid_1d(int64_t work) {
 using SweepKey = std::tuple<const void*, const void*, int, long long, int, unsigned, unsigned, int>;
 static std::mutex g_hmu;
 static std::map<SweepKey, int> g_hist;
+// The delta base width sampled from a weight array (by its address and arc
+// count): later solves of the same weights skip the sample, a chain of
+// random loads on as many pages that otherwise sets the init launch's length.
+// Only bucket widths depend on it, never a fixpoint.
+static std::map<std::pair<const void*, long long>, int> g_dbase;
 constexpr int FIRST_BATCH = 16;
 
 // jobs != nullptr: the pull form of job scheduling (in-CSR = predecessor
@@ -1692,6 +1705,12 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
         ev1 = timing_event(1);
         if (!ev0 || !ev1) return fail(LLP_E_HIP, "hipEventCreate failed");
         LLP_HIP(hipEventRecord(ev0, st));
+    }
+    const std::pair<const void*, long long> wkey((const void*)a.in_w, (long long)g->m);
+    if (!a.unit_w && !a.jobs && a.in_w) {
+        std::lock_guard<std::mutex> lk(g_hmu);
+        auto it = g_dbase.find(wkey);
+        if (it != g_dbase.end()) a.dbase_known = it->second;
     }
     const int g1 = launch_grid_1d(g->n > g->m ? g->n : g->m);
     hipLaunchKernelGGL(k_graph_init, dim3(launch_grid_1d(g->n)), dim3(256), 0, st, a, o.warm_start);
@@ -1820,6 +1839,11 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
         std::lock_guard<std::mutex> lk(g_hmu);
         if (g_hist.size() >= 256) g_hist.clear();
         g_hist[hkey] = h.end_k + 1;
+    }
+    if (!a.unit_w && !a.jobs && a.in_w && a.dbase_known <= 0 && h.dbase > 0) {
+        std::lock_guard<std::mutex> lk(g_hmu);
+        if (g_dbase.size() >= 256) g_dbase.clear();
+        g_dbase[wkey] = h.dbase;
     }
     if (o.stats) {
         memset(o.stats, 0, sizeof(*o.stats));
