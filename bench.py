@@ -197,21 +197,23 @@ def run_step(llp, dg, src, ws, dist, lev, kw, timing, log=None):
         trace = llp.trace_buffer(8192)
         fn(dg, src, out=out, ws=ws, stats=st, trace=trace, **k)
         rec = llp.trace_records(trace, int(st.rounds))
-        log.append({"solve": name, "modes": [int(c) for c in rec["mode"]]})
+        log.append({"solve": name, "modes": [int(c) for c in rec["mode"]], "bitmap_rounds": int(st.bitmap_rounds)})
     return s1, s2
 
 
-def kernel_bytes(s, weighted):
+def kernel_bytes(s, weighted, n):
     """Algorithmic bytes of the MAIN (pull evaluation) and PRE (expansion / push)
     kernels of one solve: MAIN reads per in-arc the source id and the weight
     (SSSP; 8 / 4 B), per gathered tail state 4 B (a dense round does not
     gather the arcs that cannot improve their row) and 16 B per candidate
-    entry; PRE reads 16 B per changed entry, per expansion arc the target id
-    and its stamp (8 B), per push arc the target id, weight and state
-    (12 / 8 B)."""
+    entry, and a BFS bitmap round reads the n-bit bitmap once; PRE reads 16 B
+    per changed entry, per expansion arc the target id and its stamp (8 B),
+    per push arc the target id, weight and state (12 / 8 B), and for a bitmap
+    round the n states (4 B each) and writes the bitmap."""
     arc = 12 if weighted else 8
-    main = (arc - 4) * s.edges_inspected + 4 * s.states_gathered + 16 * s.candidates
-    pre = 16 * s.advances + 8 * s.expand_edges + arc * s.push_edges
+    bm = s.bitmap_rounds * (n // 8)
+    main = (arc - 4) * s.edges_inspected + 4 * s.states_gathered + 16 * s.candidates + bm
+    pre = 16 * s.advances + 8 * s.expand_edges + arc * s.push_edges + s.bitmap_rounds * 4 * n + bm
     return main, pre
 
 
@@ -265,8 +267,9 @@ def step_phases(d):
     --profile-steps run: the solves are cut at k_graph_init, the last ones
     paired with the round log, and each solve's step launches before its
     first multi-round (tail) launch mapped to its rounds in order (a push
-    round one PRE launch, a dense round one MAIN launch, a pull round PRE then
-    MAIN; launches past the last round are no-ops).  Returns {phase: [dispatch]}
+    round one PRE launch, a dense round one MAIN launch, a pull round and a
+    BFS bitmap dense round PRE then MAIN; launches past the last round are
+    no-ops).  Returns {phase: [dispatch]}
     with phases pre, main, tail (the multi-round launches) and after_tail
     (step launches after one, not mapped)."""
     import re
@@ -284,9 +287,14 @@ def step_phases(d):
     out = {"pre": [], "main": [], "tail": [], "after_tail": []}
     for launches, ent in zip(solves[-len(log):], log):
         want = []
+        ndense = sum(1 for code in ent["modes"] if code & 3 == 1)
+        nbm = ent.get("bitmap_rounds", 0)
+        if nbm not in (0, ndense):
+            raise SystemExit(f"{d}: {nbm} bitmap rounds among {ndense} dense rounds: launches not mappable")
         for code in ent["modes"]:
             mode = code & 3
-            want += ["pre", "main"] if mode == 0 else (["main"] if mode == 1 else ["pre"])
+            dense = ["pre", "main"] if nbm else ["main"]
+            want += ["pre", "main"] if mode == 0 else (dense if mode == 1 else ["pre"])
         i = 0
         for j, rec in enumerate(launches):
             if "k_graph_tail" in rec[1]:
@@ -455,7 +463,7 @@ def main():
     ml = pl = 0
     for s1, s2 in recs:
         for s, weighted in ((s1, True), (s2, False)):
-            x, y = kernel_bytes(s, weighted)
+            x, y = kernel_bytes(s, weighted, n)
             mb += x
             pb += y
             mt += s.kernel_ms

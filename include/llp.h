@@ -94,7 +94,7 @@ typedef struct {
     int64_t advances;         /* entries of the changed lists consumed (indices advanced) */
     int64_t expand_edges;     /* out-arcs read by successor expansion */
     int64_t eval_launches;    /* step launches that evaluated a pull or dense round (LLP_TIMING; a dense
-                                 round is decided and evaluated in one launch) */
+                                 round is decided and evaluated in one launch, a bitmap round in two) */
     float device_ms;          /* whole solve on the stream (LLP_TIMING) */
     float kernel_ms;          /* summed duration of the evaluation (MAIN) kernel launches (LLP_TIMING) */
     int64_t push_edges;       /* out-arcs read by push rounds */
@@ -102,7 +102,11 @@ typedef struct {
     float pre_ms;             /* summed duration of the PRE kernel launches (LLP_TIMING) */
     float pad;
     int64_t states_gathered;  /* tail states read by pull rounds: edges_inspected less the arcs a dense
-                                 round proves unable to improve their row (not gathered) */
+                                 round proves unable to improve their row (not gathered), and less
+                                 every arc of a bitmap round */
+    int64_t bitmap_rounds;    /* BFS dense rounds that looked their tails up in a bitmap of n bits
+                                 (built from the state array by the round's first launch) instead of
+                                 gathering tail states; such a round takes two step launches */
 } llp_stats;
 
 /* One record per round when LLP_TRACE is set (device buffer of trace_cap records). */

@@ -50,7 +50,8 @@ class Stats(ctypes.Structure):
                 ("expand_edges", ctypes.c_int64), ("eval_launches", ctypes.c_int64),
                 ("device_ms", ctypes.c_float), ("kernel_ms", ctypes.c_float),
                 ("push_edges", ctypes.c_int64), ("pre_launches", ctypes.c_int64),
-                ("pre_ms", ctypes.c_float), ("pad", ctypes.c_float), ("states_gathered", ctypes.c_int64)]
+                ("pre_ms", ctypes.c_float), ("pad", ctypes.c_float), ("states_gathered", ctypes.c_int64),
+                ("bitmap_rounds", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

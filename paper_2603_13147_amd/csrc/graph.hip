@@ -53,9 +53,11 @@ struct GCtrl {
     int decoded;        // the launch that found the end decoded G in place
     int carried[2];     // entries carried by the delta filter, by round parity (traced solves)
     int step_phase[2];  // step kernel k: phase[k & 1] 0 = PRE of round step_round + 1, 1 = MAIN of step_round
+                        // (2: MAIN of a BFS dense round evaluated with the bitmap)
     int step_round[2];
     int diag[8];        // first guard event: site, index, bound, context
     long long rounds, cand, edges, adv, xedges, pedges, gath;
+    long long bmr;      // BFS dense rounds evaluated with the bitmap
     SchedHist hist[2];  // scheduler history, double-buffered by round parity
     int stop[2];        // step launch k returns at once when stop[k & 1] is set (see k_graph_step)
     unsigned tail_bar;  // barrier counter of a tail launch (cleared before each)
@@ -90,6 +92,7 @@ struct GArgs {
     long long max_rounds;
     SchedParams sp;
     int dbase_known;       // > 0: the delta base width of these weights, sampled by an earlier solve
+    unsigned long long* bm;   // BFS dense rounds: bit v set iff d(v) <= dmin of the round (n bits)
 };
 
 __device__ __forceinline__ ListRef cl_of(const GArgs& a, int r) { return (r & 1) ? a.cl1 : a.cl0; }
@@ -336,6 +339,18 @@ __device__ __forceinline__ void arc_cands(const GArgs& a, const int* u, const in
     }
 }
 
+// BFS dense round with the bitmap: an arc from a marked tail (distance at
+// most dmin) offers its row exactly the cap INF - (dmin + 1); other arcs
+// offer nothing this round (their tails are carried, see pre_phase).
+template <int N>
+__device__ __forceinline__ void arc_cands_bm(const GArgs& a, const int* u, const bool* act, int* c, int cap) {
+    unsigned long long b[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) b[j] = a.bm[u[j] >> 6];
+#pragma unroll
+    for (int j = 0; j < N; ++j) c[j] = (act[j] && ((b[j] >> (u[j] & 63)) & 1ull)) ? cap : 0;
+}
+
 // State of rows v .. v+63, one per lane: in-row bounds, value, out-row bounds.
 struct RowWin {
     int pl, pn, g, ob, oe;
@@ -391,9 +406,11 @@ __device__ __forceinline__ void row_advance(const GArgs& a, int r, int v, int x,
 // row is split between waves, another may already have reached the cap).
 // thr: only arcs of weight below it can improve the row (see dense_dmin);
 // the others are not gathered.  nrd: arcs read, nins: states gathered.
+template <bool BM>
 __device__ __forceinline__ int row_max(const GArgs& a, int lo, int hi, bool& ovf, int cap, int v, bool gv_live,
                                        int thr, int& nrd, int& nins) {
     const int l = lane();
+    constexpr bool look = BM;
     const bool weighted = !a.unit_w && !a.jobs;
     int x = 0;
     bool bad = false;
@@ -418,10 +435,11 @@ __device__ __forceinline__ int row_max(const GArgs& a, int lo, int hi, bool& ovf
                 act[j] = false;
                 u[j] = 0;
             }
-            nins += act[j] ? 1 : 0;
+            if constexpr (!look) nins += act[j] ? 1 : 0;   // bitmap lookups gather no state
             u[j] = clampi(u[j], a.n, bad);
         }
-        arc_cands<8>(a, u, w, act, c, ovf);
+        if constexpr (look) arc_cands_bm<8>(a, u, act, c, cap);
+        else arc_cands<8>(a, u, w, act, c, ovf);
 #pragma unroll
         for (int j = 0; j < 8; ++j) x = max(x, c[j]);
     }
@@ -431,11 +449,14 @@ __device__ __forceinline__ int row_max(const GArgs& a, int lo, int hi, bool& ovf
 
 // Dense evaluation of one wave's arc range [wb, we): every row whose first
 // in-arc lies in the range (rows of up to DLONG arcs are evaluated whole,
-// even past we) and the part inside the range of any longer row.
+// even past we) and the part inside the range of any longer row.  BM: a BFS
+// round whose tails are looked up in the bitmap instead of gathered.
+template <bool BM>
 __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef& out, GShared& sh, int* cb,
                            bool& ovf, long long& nadv, int& lmin, int cap, int dlo, int& nrd, int& nins) {
     if (wb >= we) return;
     const int l = lane();
+    constexpr bool look = BM;
     DenseSrc ds{a.in_ptr, a.n, a.ctrl->diag};
     int v = ds.locate(wb).s;
     RowWin R = load_rows(a, v);
@@ -450,7 +471,7 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
             const RowWin Rn = load_rows(a, v + 1);
             if (d0 > DLONG) {
                 const int g0 = shfl(R.g, 0);
-                const int x = g0 >= cap ? 0 : row_max(a, wb, min(we, P1), ovf, cap, v, true, arc_bound(g0, dlo), nrd, nins);
+                const int x = g0 >= cap ? 0 : row_max<BM>(a, wb, min(we, P1), ovf, cap, v, true, arc_bound(g0, dlo), nrd, nins);
                 row_advance(a, r, v, x, shfl(R.g, 0), shfl(R.ob, 0), shfl(R.oe, 0), false, out, sh, nadv, lmin);
             }
             R = Rn;
@@ -463,7 +484,7 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
             const RowWin Rn = load_rows(a, v + 1);
             const int hi = d0 <= DLONG ? P1 : min(we, P1);
             const int g0 = shfl(R.g, 0);
-            const int x = g0 >= cap ? 0 : row_max(a, P0, hi, ovf, cap, v, hi != P1, arc_bound(g0, dlo), nrd, nins);
+            const int x = g0 >= cap ? 0 : row_max<BM>(a, P0, hi, ovf, cap, v, hi != P1, arc_bound(g0, dlo), nrd, nins);
             row_advance(a, r, v, x, shfl(R.g, 0), shfl(R.ob, 0), shfl(R.oe, 0), hi == P1, out, sh, nadv, lmin);
             R = Rn;
             ++v;
@@ -552,10 +573,11 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
                 act[j] = false;
                 u[j] = 0;
             }
-            nins += act[j] ? 1 : 0;
+            if constexpr (!look) nins += act[j] ? 1 : 0;
             u[j] = clampi(u[j], a.n, bad);
         }
-        arc_cands<8>(a, u, w, act, c, ovf);
+        if constexpr (look) arc_cands_bm<8>(a, u, act, c, cap);
+        else arc_cands<8>(a, u, w, act, c, ovf);
 #pragma unroll
         for (int j = 0; j < 8; ++j) cb[l + 64 * j] = c[j];   // positions past the block are never read
         if (bad) record_diag(a.ctrl->diag, 46, v, P0, C, a.n);
@@ -1004,12 +1026,78 @@ __device__ __forceinline__ int delta_of(const GArgs& a, int code) {
     }
 }
 
+__device__ int dense_cap(const GArgs& a, int r, GShared& sh);
+
+// PRE launch of a BFS dense round r evaluated with the bitmap (cap = INF -
+// (dmin + 1), dmin the smallest distance in CL[r-1]).  Bit v of a.bm is set
+// iff d(v) <= dmin: such a tail offers its head exactly the cap, which bounds
+// every row this round, and a tail with a larger distance offers less.  The
+// round evaluates only the marked tails; an entry of CL[r-1] above dmin is
+// carried into CL[r] instead, so each of its arcs that this round leaves
+// unsatisfied keeps its tail listed (invariant I), and an unlisted tail's
+// arcs are satisfied already.  Marks do not change within the round: rows
+// advance to dmin + 1 at most.
+constexpr int BM_SCAN = 16;    // bitmap words per wave per pass
+constexpr int BM_CARRY = 8;    // list entries per thread per pass
+__device__ void bm_prepare(const GArgs& a, int r, int cap, const ListRef& in, const ListRef& out, GShared& sh) {
+    const int l = lane();
+    const long long words = ((long long)a.n + 63) >> 6;
+    const long long W = (long long)gridDim.x * GW;
+    // 16 words per wave in flight: the scan is one or two passes
+    for (long long c = (long long)blockIdx.x * GW + (threadIdx.x >> 6); c < words; c += BM_SCAN * W) {
+        int g[BM_SCAN];
+#pragma unroll
+        for (int j = 0; j < BM_SCAN; ++j) {
+            const long long v = (c + j * W) * 64 + l;
+            g[j] = v < a.n ? a.G[v] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < BM_SCAN; ++j) {
+            const unsigned long long b = ballot(g[j] > cap);
+            if (l == 0 && c + j * W < words) a.bm[c + j * W] = b;
+        }
+    }
+    const int cnt = min(sh.cnt[blockIdx.x], in.cap);
+    const int4* ent = in.ent + (long long)blockIdx.x * in.cap;
+    int dmn = LLP_INF;
+    for (int base = 0; base < cnt; base += BM_CARRY * GB) {
+        int4 e[BM_CARRY];
+        int g[BM_CARRY];
+#pragma unroll
+        for (int j = 0; j < BM_CARRY; ++j) {
+            const int i = base + j * GB + (int)threadIdx.x;
+            e[j] = i < cnt ? ent[i] : make_int4(-1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < BM_CARRY; ++j) g[j] = e[j].x >= 0 ? a.G[guard(e[j].x, a.n, a.ctrl->diag, 68)] : LLP_INF;
+#pragma unroll
+        for (int j = 0; j < BM_CARRY; ++j) {
+            const bool put = e[j].x >= 0 && g[j] <= cap;   // d > dmin
+            if (put) {
+                amax(&a.cstamp[guard(e[j].x, a.n, a.ctrl->diag, 68)], r);
+                dmn = min(dmn, LLP_INF - g[j]);
+            }
+            append(put, e[j].x, e[j].y, e[j].w, &sh.ctr, out, &a.ctrl->status);
+            const int nput = __popcll(ballot(put));
+            if (l == 0 && nput && a.trace) atomicAdd(&sh.carried, nput);
+        }
+    }
+    if (out.segmin) wave_min_to_lds(true, dmn, &sh.cmin);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        publish(out, sh.ctr, sh.cmin);   // MAIN appends after the carried entries
+        if (sh.carried) atomicAdd(&a.ctrl->carried[r & 1], sh.carried);
+    }
+}
+
 // --------------------------------------------------------------- PRE
 // Round r, first phase: consume CL[r-1], decide the round's code, then
 // expand into WL (pull) or push (CL[r]); returns the code of a dense round,
 // whose evaluation follows in the same launch, else -1.  k: step launch.
-template <bool LQ>
-__device__ int pre_phase(const GArgs& a, int r, int k, GShared& sh) {
+// BM: a bounded BFS dense round prepares the bitmap here and is evaluated by
+// the next launch.
+template <bool LQ, bool BM>
+__device__ __forceinline__ int pre_phase(const GArgs& a, int r, int k, GShared& sh) {
     const ListRef in = cl_of(a, r - 1);
     const ListRef out = cl_of(a, r);
     // the learned schedule's inputs besides the list totals (its weights and
@@ -1078,16 +1166,21 @@ __device__ int pre_phase(const GArgs& a, int r, int k, GShared& sh) {
         const int dmin = load_segmin(in.segmin, a.nseg, &sh.tmp1);
         hi = ((long long)dmin / delta) * delta + delta;
     }
+    // the same bound the evaluation computes from the same list (dense_cap)
+    const int bcap = (BM && mode == MODE_DENSE && !(r == 1 && a.warm_dense)) ? dense_cap(a, r, sh) : LLP_INF;
+    const bool bmr = bcap != LLP_INF;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         GCtrl* c = a.ctrl;
         c->mode = code;
         c->rounds = r;
-        // the next step launch: MAIN of a pull round, else PRE of the next round
-        // (a dense round is evaluated in this launch)
-        c->step_phase[(k + 1) & 1] = mode == MODE_PULL ? 1 : 0;
+        // the next step launch: MAIN of a pull round or of a bitmap dense
+        // round, else PRE of the next round (a dense round is evaluated in
+        // this launch)
+        c->step_phase[(k + 1) & 1] = mode == MODE_PULL ? 1 : (bmr ? 2 : 0);
         c->step_round[(k + 1) & 1] = r;
         if (a.plog && k < a.plog_cap) a.plog[k] = 0;
         c->adv += sh.tot_count;
+        if (bmr) c->bmr++;
         if (mode == MODE_PULL) c->xedges += sh.tot_edges;
         if (mode == MODE_PUSH) c->pedges += sh.tot_edges;
         hist_push(c->hist[r & 1], c->hist[(r + 1) & 1], r, mode, sh.tot_count, sh.tot_edges);
@@ -1104,7 +1197,13 @@ __device__ int pre_phase(const GArgs& a, int r, int k, GShared& sh) {
             a.trace[r - 1] = t;
         }
     }
-    if (mode == MODE_DENSE) return code;   // evaluated by the caller in this launch
+    if (mode == MODE_DENSE) {
+        if (bmr) {
+            bm_prepare(a, r, bcap, in, out, sh);
+            return -1;
+        }
+        return code;   // evaluated by the caller in this launch
+    }
     SegView sv{in.ent, in.cap, a.nseg, sh.cnt, sh.epre, sh.tot_edges, sh.tot_count};
     ListSrc src{sv, a.ctrl->diag};
     int wb, we;
@@ -1175,7 +1274,11 @@ __device__ int dense_dmin(const GArgs& a, int r, GShared& sh) {
 // Round r, second phase (pull and dense rounds): evaluate WL (or every
 // vertex) and produce CL[r].  verify != 0: a dense round on the final state
 // that must change nothing.
-__device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh, int round_code) {
+// bmr: a BFS dense round whose PRE launch built the bitmap and carried the
+// entries above dmin into CL[r] (this launch appends after them); BM: the
+// kernel evaluates every dense round so (see bm_prepare).
+template <bool BM>
+__device__ __forceinline__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh, int round_code, bool bmr) {
     const int code = verify ? MODE_DENSE : round_code;
     const int mode = code & 3;
     if (!verify && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1186,8 +1289,8 @@ __device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh
     if (mode == MODE_PUSH) return;
     const ListRef out = verify ? a.wl : cl_of(a, r);   // verify writes into WL's storage
     if (threadIdx.x == 0) {
-        // pull rounds continue the segment PRE started with carried entries
-        const bool cont = mode == MODE_PULL && !verify;
+        // pull rounds (and bitmap rounds) continue the segment PRE started with carried entries
+        const bool cont = (mode == MODE_PULL || bmr) && !verify;
         sh.ctr = cont ? out.seg[blockIdx.x] : 0ull;
         sh.cmin = (cont && out.segmin) ? out.segmin[blockIdx.x] : LLP_INF;
         sh.cnt_rd = 0ull;
@@ -1213,7 +1316,13 @@ __device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh
         wave_range(a.m, wb, we);
         int lmin = LLP_INF;
         int nrd = 0, nins = 0;
-        dense_wave(a, rr, wb, we, out, sh, sh.dcb[threadIdx.x >> 6], ovf, nadv, lmin, cap, dlo, nrd, nins);
+        if (BM && !bmr && !verify) {
+            // the bitmap kernel runs only sweeps whose dense rounds are all
+            // bounded (BFS without a warm start): an unbounded one is a fault
+            if (blockIdx.x == 0 && threadIdx.x == 0) set_status(&a.ctrl->status, LLP_E_HIP);
+        } else {
+            dense_wave<BM>(a, rr, wb, we, out, sh, sh.dcb[threadIdx.x >> 6], ovf, nadv, lmin, cap, dlo, nrd, nins);
+        }
         if ((cap != LLP_INF || dlo >= 0) && !verify) {
             // arcs read and states gathered: summed per workgroup in LDS, one
             // atomic each per workgroup
@@ -1270,7 +1379,7 @@ __device__ void main_phase(const GArgs& a, int r, int verify, int k, GShared& sh
 // have bucketed rounds; without them a bucketed push round continues chains
 // instead, and the kernel is smaller, which the dense rounds measurably
 // prefer).
-template <bool LQ>
+template <bool LQ, bool BM>
 __global__ void __launch_bounds__(GB, 4) k_graph_step(GArgs a, int k) {
     __shared__ GShared sh;
     if (ld_relaxed(&a.ctrl->stop[k & 1]) || ld_relaxed(&a.ctrl->status)) {
@@ -1282,12 +1391,12 @@ __global__ void __launch_bounds__(GB, 4) k_graph_step(GArgs a, int k) {
     int r = rr, code;
     if (ph == 0) {
         r = rr + 1;
-        code = pre_phase<LQ>(a, r, k, sh);
+        code = pre_phase<LQ, BM>(a, r, k, sh);
         if (code < 0) return;
     } else {
         code = a.ctrl->mode;
     }
-    main_phase(a, r, 0, k, sh, code);
+    main_phase<BM>(a, r, 0, k, sh, code, ph == 2);
 }
 
 // --------------------------------------------------------------- tail
@@ -1473,7 +1582,7 @@ __global__ void k_graph_tail_reset(GCtrl* c) {
 
 __global__ void __launch_bounds__(GB) k_graph_verify(GArgs a, int r) {
     __shared__ GShared sh;
-    main_phase(a, r, 1, 0, sh, MODE_DENSE);
+    main_phase<false>(a, r, 1, 0, sh, MODE_DENSE, false);
 }
 
 // --------------------------------------------------------------- finish
@@ -1546,6 +1655,7 @@ static size_t graph_ws(int64_t n, int64_t m, int per_cu, GArgs* a, char* base, s
     Carver cv{base, cap, 0, base == nullptr};
     int* stamp = cv.take<int>(n);
     int* cstamp = cv.take<int>(n);
+    unsigned long long* bm = cv.take<unsigned long long>((n + 63) / 64);
     GCtrl* ctrl = cv.take<GCtrl>(1);
     const long long plog_cap = 8 * n + 512;   // covers the default round limit's launches
     signed char* plog = cv.take<signed char>(plog_cap);
@@ -1562,6 +1672,7 @@ static size_t graph_ws(int64_t n, int64_t m, int per_cu, GArgs* a, char* base, s
     if (a) {
         a->stamp = stamp;
         a->cstamp = cstamp;
+        a->bm = bm;
         a->ctrl = ctrl;
         a->wl = lists[0];
         a->cl0 = lists[1];
@@ -1616,9 +1727,11 @@ static bool coop_supported() {
     return ok;
 }
 
-static void launch_step(const GArgs& a, int k, bool lq, hipStream_t st) {
-    if (lq) hipLaunchKernelGGL(k_graph_step<true>, dim3(a.nseg), dim3(GB), 0, st, a, k);
-    else hipLaunchKernelGGL(k_graph_step<false>, dim3(a.nseg), dim3(GB), 0, st, a, k);
+// lq: the kernel with local queues; bm: BFS dense rounds with the bitmap
+static void launch_step(const GArgs& a, int k, bool lq, bool bm, hipStream_t st) {
+    if (lq) hipLaunchKernelGGL((k_graph_step<true, false>), dim3(a.nseg), dim3(GB), 0, st, a, k);
+    else if (bm) hipLaunchKernelGGL((k_graph_step<false, true>), dim3(a.nseg), dim3(GB), 0, st, a, k);
+    else hipLaunchKernelGGL((k_graph_step<false, false>), dim3(a.nseg), dim3(GB), 0, st, a, k);
 }
 
 static int launch_grid_1d(int64_t work) {
@@ -1744,6 +1857,8 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
     // the step kernel with local queues where bucketed push rounds can occur
     const bool lq_kernel = !jobs_dur && (a.sp.push_dclass == DCLS_WIDE || o.sched == LLP_SCHED_RANDOM ||
                                          o.sched == LLP_SCHED_SCRIPT || (o.sched == LLP_SCHED_FIXED && o.delta > 0));
+    // BFS sweeps: bounded dense rounds look tails up in a bitmap
+    const bool bm_kernel = bfs && !jobs_dur && !lq_kernel && !o.warm_start;
     // the multi-round tail: push rounds (hybrid, fixed push, learned), graphs
     // whose grid splits evenly over the XCDs, a device with cooperative launches
     bool tail_ok = !jobs_dur && a.nseg % TAIL_XCDS == 0 && a.sp.can_push &&
@@ -1762,12 +1877,12 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
                 hipEvent_t e1 = timing_event(3 + evs.size());
                 if (!e0 || !e1) return fail(LLP_E_HIP, "hipEventCreate failed");
                 LLP_HIP(hipEventRecord(e0, st));
-                launch_step(a, (int)k, lq_kernel, st);
+                launch_step(a, (int)k, lq_kernel, bm_kernel, st);
                 LLP_HIP(hipEventRecord(e1, st));
                 evs.push_back(e0);
                 evs.push_back(e1);
             } else {
-                launch_step(a, (int)k, lq_kernel, st);
+                launch_step(a, (int)k, lq_kernel, bm_kernel, st);
             }
         }
         // without verification, the step launch that finds the end decodes
@@ -1851,6 +1966,7 @@ static int solve_graph_core(const llp_graph* g, int32_t source, int32_t* out, co
         o.stats->candidates = h.cand;
         o.stats->edges_inspected = h.edges;
         o.stats->states_gathered = h.gath;
+        o.stats->bitmap_rounds = h.bmr;
         o.stats->advances = h.adv;
         o.stats->expand_edges = h.xedges;
         o.stats->push_edges = h.pedges;

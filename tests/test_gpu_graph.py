@@ -225,8 +225,9 @@ def test_dense_bound_counts():
     """Dense rounds gather only the arcs that can still improve their row:
     SSSP skips an arc of weight w into a row at distance d when
     dmin + w >= d (dmin the smallest distance of the previous changed list),
-    a BFS dense round stops long rows at the bound INF - (dmin + 1); both
-    count only what they gathered, and reach the oracle's fixpoint."""
+    a BFS dense round stops long rows at the bound INF - (dmin + 1) and looks
+    tails up in a bitmap instead of gathering their states; both count only
+    what they gathered, and reach the oracle's fixpoint."""
     g = llpgen.rmat_graph(14, seed=41)
     s = llpgen.max_outdeg_source(g)
     _, dg = dev_graph(g)
@@ -241,7 +242,29 @@ def test_dense_bound_counts():
     got = run(llp.bfs, dg, s, sched=llp.SCHED_FIXED, flags=llp.DENSE, stats=sb)
     assert np.array_equal(got, oracle.bfs(g.n, g.src, g.dst, s, bag=True))
     assert 0 < sb.edges_inspected < sb.rounds * g.m
-    assert sb.states_gathered == sb.edges_inspected
+    # every round is bounded, so every one looks its tails up in the bitmap
+    # and gathers no state
+    assert sb.bitmap_rounds == sb.rounds
+    assert sb.states_gathered == 0
+
+
+def test_bfs_bitmap_round_carries():
+    """A BFS dense round with the bitmap right after a push round whose
+    chains reached past the next level: the list entries above the round's
+    smallest distance are carried into the next list (counted in the trace's
+    pending field), and the sweep reaches the oracle's levels."""
+    g = llpgen.rmat_graph(16, seed=43)
+    s = llpgen.max_outdeg_source(g)
+    _, dg = dev_graph(g)
+    st = llp.Stats()
+    trace = llp.trace_buffer(4096)
+    got = run(llp.bfs, dg, s, sched=llp.SCHED_HYBRID, flags=llp.TRACE, stats=st, trace=trace)
+    assert np.array_equal(got, oracle.bfs(g.n, g.src, g.dst, s, bag=True))
+    rec = llp.trace_records(trace, int(st.rounds))
+    modes = [int(c) & 3 for c in rec["mode"]]
+    assert modes[0] == 2 and modes[1] == 1          # push, then dense
+    assert st.bitmap_rounds >= 1
+    assert int(rec["pending"][1]) > 0               # the dense round carried entries
 
 
 @pytest.mark.parametrize("kind", ["sssp", "bfs"])
