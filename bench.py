@@ -197,7 +197,8 @@ def run_step(llp, dg, src, ws, dist, lev, kw, timing, log=None):
         trace = llp.trace_buffer(8192)
         fn(dg, src, out=out, ws=ws, stats=st, trace=trace, **k)
         rec = llp.trace_records(trace, int(st.rounds))
-        log.append({"solve": name, "modes": [int(c) for c in rec["mode"]], "bitmap_rounds": int(st.bitmap_rounds)})
+        log.append({"solve": name, "modes": [int(c) for c in rec["mode"]],
+                    "bitmap": [int(b) for b in rec["bitmap"]]})
     return s1, s2
 
 
@@ -268,8 +269,8 @@ def step_phases(d):
     paired with the round log, and each solve's step launches before its
     first multi-round (tail) launch mapped to its rounds in order (a push
     round one PRE launch, a dense round one MAIN launch, a pull round and a
-    BFS bitmap dense round PRE then MAIN; launches past the last round are
-    no-ops).  Returns {phase: [dispatch]}
+    BFS dense round with the bitmap (marked in the trace) PRE then MAIN; launches
+    past the last round are no-ops).  Returns {phase: [dispatch]}
     with phases pre, main, tail (the multi-round launches) and after_tail
     (step launches after one, not mapped)."""
     import re
@@ -287,13 +288,9 @@ def step_phases(d):
     out = {"pre": [], "main": [], "tail": [], "after_tail": []}
     for launches, ent in zip(solves[-len(log):], log):
         want = []
-        ndense = sum(1 for code in ent["modes"] if code & 3 == 1)
-        nbm = ent.get("bitmap_rounds", 0)
-        if nbm not in (0, ndense):
-            raise SystemExit(f"{d}: {nbm} bitmap rounds among {ndense} dense rounds: launches not mappable")
-        for code in ent["modes"]:
+        for code, bm in zip(ent["modes"], ent["bitmap"]):
             mode = code & 3
-            dense = ["pre", "main"] if nbm else ["main"]
+            dense = ["pre", "main"] if bm else ["main"]
             want += ["pre", "main"] if mode == 0 else (dense if mode == 1 else ["pre"])
         i = 0
         for j, rec in enumerate(launches):

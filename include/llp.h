@@ -105,8 +105,9 @@ typedef struct {
                                  round proves unable to improve their row (not gathered), and less
                                  every arc of a bitmap round */
     int64_t bitmap_rounds;    /* BFS dense rounds that looked their tails up in a bitmap of n bits
-                                 (built from the state array by the round's first launch) instead of
-                                 gathering tail states; such a round takes two step launches */
+                                 (marked: distance <= the smallest of the input list), built from the
+                                 state array by a step launch of the round's own, instead of gathering
+                                 tail states; such a round takes two step launches */
 } llp_stats;
 
 /* One record per round when LLP_TRACE is set (device buffer of trace_cap records). */
@@ -118,7 +119,11 @@ typedef struct {
     int64_t in_edges;         /* out-arcs of the input list */
     int64_t out_edges;        /* pull rounds: in-arcs of the candidates */
     int32_t bucket;           /* delta-bucket floor (distance) or -1 */
-    int32_t pending;          /* changed vertices carried to the next round by the delta filter */
+    int32_t pending;          /* changed vertices carried to the next round by the delta filter (and by a
+                                 BFS bitmap round) */
+    int32_t bitmap;           /* 1: a BFS dense round evaluated with the bitmap (two step launches;
+                                 see llp_stats.bitmap_rounds) */
+    int32_t pad;
 } llp_trace_rec;
 
 typedef struct {

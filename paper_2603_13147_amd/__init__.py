@@ -60,12 +60,14 @@ class Stats(ctypes.Structure):
 class TraceRec(ctypes.Structure):
     _fields_ = [("round", ctypes.c_int32), ("mode", ctypes.c_int32), ("in_count", ctypes.c_int32),
                 ("out_count", ctypes.c_int32), ("in_edges", ctypes.c_int64), ("out_edges", ctypes.c_int64),
-                ("bucket", ctypes.c_int32), ("pending", ctypes.c_int32)]
+                ("bucket", ctypes.c_int32), ("pending", ctypes.c_int32), ("bitmap", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 TRACE_DTYPE = np.dtype([("round", np.int32), ("mode", np.int32), ("in_count", np.int32),
                         ("out_count", np.int32), ("in_edges", np.int64), ("out_edges", np.int64),
-                        ("bucket", np.int32), ("pending", np.int32)])
+                        ("bucket", np.int32), ("pending", np.int32), ("bitmap", np.int32),
+                        ("pad", np.int32)])
 
 
 class Opts(ctypes.Structure):

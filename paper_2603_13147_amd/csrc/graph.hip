@@ -1194,6 +1194,8 @@ __device__ __forceinline__ int pre_phase(const GArgs& a, int r, int k, GShared& 
             t.out_edges = 0;
             t.bucket = hi > 0 ? (int)(hi - delta) : -1;
             t.pending = 0;
+            t.bitmap = bmr ? 1 : 0;
+            t.pad = 0;
             a.trace[r - 1] = t;
         }
     }
@@ -1553,6 +1555,8 @@ __global__ void __launch_bounds__(GB, 4) k_graph_tail(GArgs a, int k) {
                 tr.out_edges = 0;
                 tr.bucket = hi > 0 ? (int)(hi - delta) : -1;
                 tr.pending = 0;
+                tr.bitmap = 0;
+                tr.pad = 0;
                 a.trace[r - 1] = tr;
             }
         }

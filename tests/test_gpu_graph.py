@@ -205,7 +205,7 @@ def test_verify_and_stats_and_trace():
     g = llpgen.uniform_graph(4096, 32768, 1, 100, seed=2)
     _, dg = dev_graph(g)
     st = llp.Stats()
-    trace = torch.zeros(4096 * 40, dtype=torch.uint8, device="cuda")
+    trace = llp.trace_buffer(4096)
     got = run(llp.sssp, dg, 0, flags=llp.VERIFY | llp.TRACE | llp.TIMING, stats=st, trace=trace)
     assert np.array_equal(got, oracle.sssp(g.n, g.src, g.dst, g.w, 0))
     assert st.rounds > 2 and st.edges_inspected >= g.m // 4 and st.advances >= g.n - 1
@@ -263,7 +263,7 @@ def test_bfs_bitmap_round_carries():
     rec = llp.trace_records(trace, int(st.rounds))
     modes = [int(c) & 3 for c in rec["mode"]]
     assert modes[0] == 2 and modes[1] == 1          # push, then dense
-    assert st.bitmap_rounds >= 1
+    assert st.bitmap_rounds >= 1 and int(rec["bitmap"][1]) == 1
     assert int(rec["pending"][1]) > 0               # the dense round carried entries
 
 
@@ -353,7 +353,7 @@ def test_trace_records_delta_rounds():
     g = llpgen.rmat_graph(12, seed=4)
     s = llpgen.max_outdeg_source(g)
     _, dg = dev_graph(g)
-    trace = torch.zeros(4096 * 40, dtype=torch.uint8, device="cuda")
+    trace = llp.trace_buffer(4096)
     st = llp.Stats()
     d = run(llp.sssp, dg, s, sched=llp.SCHED_FIXED, delta=64, flags=llp.TRACE, trace=trace, stats=st)
     assert np.array_equal(d, oracle.sssp(g.n, g.src, g.dst, g.w, s))
