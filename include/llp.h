@@ -142,7 +142,8 @@ typedef struct {
     int32_t chunk;              /* launch knob, 0 = default: graph sweeps: workgroups (list segments) per CU
                                    (default 2, at most 8; pass the same opts to llp_workspace_bytes);
                                    stable marriage: proposals per thread per launch; batch: instances per
-                                   queue claim */
+                                   queue claim; jobs readiness: widest level, in arcs, run by one
+                                   workgroup in LDS (default and most 1024; -1 = none) */
     int32_t block;              /* threads per workgroup; 0 = default (256) */
     llp_trace_rec* trace_dev;   /* [device] LLP_TRACE output */
     int64_t trace_cap;
@@ -215,8 +216,11 @@ int llp_solve_sm(int32_t n, const int16_t* men_pref, const int16_t* women_rank, 
    completion time is S[j] + dur[j].  pred_ptr[n+1], pred_idx[E] [device]:
    predecessor lists; succ_ptr[n+1], succ_idx[E] [device]: the same arcs
    grouped by predecessor.  dur[n] [device] >= 0.  start[n] [device, output].
-   Default schedule: the paper's readiness counters (each job fixed once);
-   LLP_JOBS_PULL: pull rounds over predecessors with successor worklists.
+   Default schedule: the paper's readiness counters (each job fixed once),
+   one launch per wide level; consecutive levels of at most 1024 arcs
+   (opts->chunk) run in one launch, by one workgroup with the level lists in
+   LDS, up to 64 levels per launch.  LLP_JOBS_PULL: pull rounds over
+   predecessors with successor worklists.
    Errors: LLP_E_ARG, LLP_E_INPUT, LLP_E_CYCLE (the arcs contain a cycle),
    LLP_E_OVERFLOW (a completion time exceeds 2^31-1). */
 int llp_solve_jobs(int32_t n, const int32_t* pred_ptr, const int32_t* pred_idx, const int32_t* dur,

@@ -17,7 +17,26 @@
 // an empty input list ends the sweep; a job whose counter never reached zero
 // lies on (or after) a cycle.  The pull form of the sweep (LLP_JOBS_PULL)
 // runs in the generic graph sweep.
+//
+// Narrow levels.  A level of at most JN_ARCS arcs (most levels of a deep DAG
+// are a few jobs wide) is run by workgroup 0 alone, which keeps running the
+// following levels in the same launch, with both lists in LDS, while they
+// stay that narrow (at most JN_LEVELS per launch, so the host's abort flag
+// and round limit are seen in time).  Its rounds are separated by a full
+// wait on its memory operations and a workgroup barrier: a job made ready in
+// round r is read in round r + 1 through agent-scope loads, after every
+// atomicMax on it has completed, so the launch boundary is not needed there.
+// The launch hands the first wide level's list to the next launch through
+// one of two small hand-over lists (alternating, so a launch never writes the
+// list it was given: a late workgroup of it may still be reading the list's
+// totals).  Every launch takes its level and its input list from the slots
+// the previous launch wrote (lvl / src, by launch parity).
 #include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "llp_host.h"
 #include "llp_lists.h"
@@ -27,14 +46,21 @@ namespace llp {
 constexpr int JB = 256;            // threads per workgroup
 constexpr int JW = JB / LLP_WAVE;  // waves per workgroup
 constexpr int J_MAX_SEG = 1024;
+constexpr int JN_ARCS = 1024;      // widest level (arcs) run in the narrow form
+constexpr int JN_LEVELS = 64;      // narrow levels per launch at most
+constexpr int JN_PER = JN_ARCS / JB;
 
 struct JCtrl {
     int done;
     int status;
     int last_round;
-    int pad;
+    int over;           // a level past the round limit had jobs to run
     int diag[8];
     long long rounds, ready, edges;
+    int lvl[2];         // launch k runs level lvl[k & 1] ...
+    int src[2];         // ... from list src[k & 1]: 0 = R[level - 1], 1 / 2 = hand-over list h0 / h1
+    int end_k;          // the launch that ended the sweep
+    int pad2;
 };
 
 struct JArgs {
@@ -47,7 +73,10 @@ struct JArgs {
     int* S;
     int* cnt;          // unfixed predecessors per job
     ListRef l0, l1;
+    ListRef h0, h1;    // hand-over lists of the narrow form (segment 0 only, JN_ARCS entries)
     int nseg;
+    int narrow;        // widest level run in the narrow form (arcs), 0 = none
+    long long max_rounds;
     JCtrl* ctrl;
 };
 
@@ -58,6 +87,14 @@ struct JShared {
     unsigned long long ctr;
     int tot_edges, tot_count;
     int tmp[JW + 1];
+    // narrow form: the current and the next level's entries {job, first
+    // successor arc, -, successor count}, per entry of the current level
+    // its first arc (exclusive prefix) and completion time
+    int4 q[2][JN_ARCS];
+    int qpre[JN_ARCS + 1];
+    int qcm[JN_ARCS];
+    int qn[2], qe[2];
+    int ovf;
 };
 
 __device__ __forceinline__ ListRef jl_of(const JArgs& a, int r) { return (r & 1) ? a.l1 : a.l0; }
@@ -73,10 +110,13 @@ __global__ void k_jobs_init(JArgs a, const int* warm) {
     for (long long s = tid; s < a.nseg; s += nt) {
         a.l0.seg[s] = 0ull;
         a.l1.seg[s] = 0ull;
+        a.h0.seg[s] = 0ull;
+        a.h1.seg[s] = 0ull;
     }
     if (tid == 0) {
         JCtrl c;
         memset(&c, 0, sizeof(c));
+        c.lvl[0] = 1;   // the first launch runs level 1 from R[0]
         *a.ctrl = c;
     }
 }
@@ -146,25 +186,192 @@ __device__ __forceinline__ void jobs_wave_range(int total, int& wb, int& we) {
     we = (int)((long long)total * (w + 1) / W);
 }
 
-__global__ void __launch_bounds__(JB) k_jobs_level(JArgs a, int r) {
+// Block-wide exclusive prefix of the successor counts of the n entries in
+// q (JN_PER per thread, in order); returns the total.
+__device__ int jn_prefix(const int4* q, int n, int* pre, int* tmp) {
+    const int t = threadIdx.x, b = t * JN_PER;
+    int d[JN_PER], sum = 0;
+#pragma unroll
+    for (int i = 0; i < JN_PER; ++i) {
+        d[i] = b + i < n ? q[b + i].w : 0;
+        sum += d[i];
+    }
+    const int incl = wave_incl_sum(sum);
+    if (lane() == LLP_WAVE - 1) tmp[t >> 6] = incl;
+    __syncthreads();
+    int before = incl - sum, tot = 0;
+    for (int w = 0; w < JW; ++w) {
+        if (w < (t >> 6)) before += tmp[w];
+        tot += tmp[w];
+    }
+#pragma unroll
+    for (int i = 0; i < JN_PER; ++i) {
+        if (b + i < n) pre[b + i] = before;
+        before += d[i];
+    }
+    __syncthreads();   // tmp is reused by the caller
+    return tot;
+}
+
+// The narrow form, run by workgroup 0 of launch k from level r (input list
+// in, holding at most JN_ARCS entries and arcs).  See the file comment.
+__device__ void jobs_narrow(const JArgs& a, int k, int r, const ListRef& in, int si, JShared& sh) {
+    JCtrl* c = a.ctrl;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        sh.qn[0] = sh.qn[1] = 0;
+        sh.qe[0] = sh.qe[1] = 0;
+        sh.ovf = 0;
+    }
+    __syncthreads();
+    // stage R[r-1] into q[0] (entries in any segments, in any order)
+    for (int sg = t; sg < a.nseg; sg += JB) {
+        const int cs = min(sh.cnt[sg], in.cap);
+        if (cs > 0) {
+            const int b = atomicAdd(&sh.qn[0], cs);
+            for (int i = 0; i < cs; ++i) sh.q[0][b + i] = in.ent[(long long)sg * in.cap + i];
+        }
+    }
+    __syncthreads();
+    int cur = 0, lv = r, levels = 0;
+    long long ready = 0, edges = 0;
+    for (;;) {
+        const int n_in = sh.qn[cur], nx = cur ^ 1;
+        // completion time of every entry (agent-scope loads: its start time
+        // was raised by atomics of this workgroup's previous round)
+        for (int i = t; i < n_in; i += JB) {
+            const int p = guard(sh.q[cur][i].x, a.n, c->diag, 74);
+            const long long cm = (long long)ld_i32<true>(a.S + p) + a.dur[p];
+            if (cm > LLP_INF) sh.ovf = 1;
+            sh.qcm[i] = cm > LLP_INF ? LLP_INF : (int)cm;
+        }
+        const int T = jn_prefix(sh.q[cur], n_in, sh.qpre, sh.tmp);
+        ready += n_in;
+        edges += T;
+        // the level's arcs, JN_PER per thread: every load before any is used
+        int j[JN_PER], cm[JN_PER];
+        bool act[JN_PER], rd[JN_PER];
+#pragma unroll
+        for (int q4 = 0; q4 < JN_PER; ++q4) {
+            const int e = t + q4 * JB;
+            act[q4] = e < T;
+            j[q4] = 0;
+            cm[q4] = 0;
+            if (act[q4]) {
+                int lo = 0, hi = n_in;   // last entry whose first arc is <= e
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (sh.qpre[mid] <= e) lo = mid;
+                    else hi = mid;
+                }
+                const int4 en = sh.q[cur][lo];
+                cm[q4] = sh.qcm[lo];
+                const int ea = guard(en.y + (e - sh.qpre[lo]), a.E, c->diag, 75, en.x);
+                j[q4] = guard(a.succ_idx[ea], a.n, c->diag, 76, ea);
+            }
+        }
+#pragma unroll
+        for (int q4 = 0; q4 < JN_PER; ++q4)
+            if (act[q4]) amax(&a.S[j[q4]], cm[q4]);
+#pragma unroll
+        for (int q4 = 0; q4 < JN_PER; ++q4) rd[q4] = act[q4] && aadd(&a.cnt[j[q4]], -1) == 1;
+#pragma unroll
+        for (int q4 = 0; q4 < JN_PER; ++q4) {
+            if (rd[q4]) {
+                const int sb = a.succ_ptr[j[q4]];
+                const int deg = a.succ_ptr[j[q4] + 1] - sb;
+                if (deg > 0) {
+                    const int idx = atomicAdd(&sh.qn[nx], 1);   // < JN_ARCS: one per arc at most
+                    atomicAdd(&sh.qe[nx], deg);
+                    sh.q[nx][idx] = make_int4(j[q4], sb, 0, deg);
+                }
+            }
+        }
+        // every atomic of the round has completed before the barrier
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        ++levels;
+        const int n_out = sh.qn[nx], e_out = sh.qe[nx];
+        const bool stop = sh.ovf != 0;
+        const bool end = n_out == 0;
+        const bool wide = e_out > a.narrow || levels >= JN_LEVELS || (long long)lv + 1 > a.max_rounds;
+        if (stop || end || wide) {
+            if (t == 0) {
+                c->rounds = lv;
+                c->ready += ready;
+                c->edges += edges;
+                if (stop) set_status(&c->status, LLP_E_OVERFLOW);
+                if (end) {
+                    c->done = 1;
+                    c->last_round = lv;
+                    c->end_k = k;
+                }
+            }
+            if (!stop && !end) {
+                // the next level's list: into the hand-over list this launch
+                // was not given, segment 0, arc offsets in order
+                const ListRef h = si == 1 ? a.h1 : a.h0;
+                const int tot = jn_prefix(sh.q[nx], n_out, sh.qpre, sh.tmp);
+                for (int i = t; i < n_out; i += JB) {
+                    int4 en = sh.q[nx][i];
+                    en.z = sh.qpre[i];
+                    h.ent[i] = en;
+                }
+                if (t == 0) {
+                    h.seg[0] = (unsigned long long)(unsigned)n_out | ((unsigned long long)(unsigned)tot << 32);
+                    c->lvl[(k + 1) & 1] = lv + 1;
+                    c->src[(k + 1) & 1] = si == 1 ? 2 : 1;
+                }
+            }
+            return;
+        }
+        if (t == 0) {
+            sh.qn[cur] = 0;
+            sh.qe[cur] = 0;
+        }
+        __syncthreads();
+        cur = nx;
+        ++lv;
+    }
+}
+
+// Launch k: level r = lvl[k & 1] from its input list; a narrow level starts
+// the narrow form in workgroup 0, and the other workgroups return.
+__global__ void __launch_bounds__(JB) k_jobs_level(JArgs a, int k) {
     __shared__ JShared sh;
     JCtrl* c = a.ctrl;
     if (ld_relaxed(&c->done) || ld_relaxed(&c->status)) return;
-    const ListRef in = jl_of(a, r - 1);
-    const ListRef out = jl_of(a, r);
+    const int r = c->lvl[k & 1], si = c->src[k & 1];
+    const ListRef in = si == 0 ? jl_of(a, r - 1) : (si == 1 ? a.h0 : a.h1);
     load_segments(in.seg, a.nseg, sh.cnt, sh.epre, sh.tmp, &sh.tot_edges, &sh.tot_count);
     if (sh.tot_count == 0) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             c->done = 1;
             c->last_round = r - 1;
+            c->end_k = k;
         }
         return;
     }
+    if ((long long)r > a.max_rounds) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            c->over = 1;
+            c->done = 1;
+            c->last_round = r - 1;
+        }
+        return;
+    }
+    if (sh.tot_edges <= a.narrow && sh.tot_count <= JN_ARCS) {
+        if (blockIdx.x == 0) jobs_narrow(a, k, r, in, si, sh);
+        return;
+    }
+    const ListRef out = jl_of(a, r);
     if (threadIdx.x == 0) sh.ctr = 0ull;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         c->rounds = r;
         c->ready += sh.tot_count;
         c->edges += sh.tot_edges;
+        c->lvl[(k + 1) & 1] = r + 1;
+        c->src[(k + 1) & 1] = 0;
     }
     __syncthreads();
     SegView sv{in.ent, in.cap, a.nseg, sh.cnt, sh.epre, sh.tot_edges, sh.tot_count};
@@ -243,11 +450,13 @@ static size_t jobs_ws(int64_t n, int64_t E, JArgs* a, char* base, size_t cap) {
     Carver cv{base, cap, 0, base == nullptr};
     int* cnt = cv.take<int>(n);
     JCtrl* ctrl = cv.take<JCtrl>(1);
-    ListRef lists[2];
-    for (int i = 0; i < 2; ++i) {
+    ListRef lists[4];
+    for (int i = 0; i < 4; ++i) {
+        // lists 2 and 3 hand a narrow launch's last list over (segment 0)
+        const int cap = i < 2 ? L.cap : JN_ARCS;
         lists[i].seg = cv.take<unsigned long long>(L.nseg);
-        lists[i].ent = cv.take<int4>((size_t)L.nseg * L.cap);
-        lists[i].cap = L.cap;
+        lists[i].ent = cv.take<int4>((size_t)L.nseg * cap);
+        lists[i].cap = cap;
         lists[i].segmin = nullptr;
     }
     if (a) {
@@ -255,6 +464,8 @@ static size_t jobs_ws(int64_t n, int64_t E, JArgs* a, char* base, size_t cap) {
         a->ctrl = ctrl;
         a->l0 = lists[0];
         a->l1 = lists[1];
+        a->h0 = lists[2];
+        a->h1 = lists[3];
         a->nseg = L.nseg;
     }
     return cv.used;
@@ -272,6 +483,12 @@ size_t jobs_workspace_bytes(int64_t n, int64_t E, int chunk) {
 int solve_jobs_pull(int32_t n, const int32_t* pred_ptr, const int32_t* pred_idx, const int32_t* dur,
                     const int32_t* succ_ptr, const int32_t* succ_idx, int32_t* start, const llp_opts* opts,
                     int64_t E);
+
+// level launches of the last sweep, by (predecessor and successor arrays, n,
+// arc count, narrow limit)
+using JobsKey = std::tuple<const void*, const void*, int, int, int>;
+static std::mutex g_jmu;
+static std::map<JobsKey, int> g_jhist;
 
 static int grid1(int64_t work) {
     int64_t g = (work + 255) / 256;
@@ -307,6 +524,8 @@ int solve_jobs(int32_t n, const int32_t* pred_ptr, const int32_t* pred_idx, cons
     a.succ_ptr = succ_ptr;
     a.succ_idx = succ_idx;
     a.S = start;
+    a.narrow = o.chunk < 0 ? 0 : (o.chunk == 0 ? JN_ARCS : std::min<int>(o.chunk, JN_ARCS));
+    a.max_rounds = o.max_rounds > 0 ? o.max_rounds : (int64_t)n + 2;
     size_t need = jobs_ws(n, E, nullptr, nullptr, 0);
     void* ws = nullptr;
     s = get_workspace(o, need, &ws);
@@ -337,19 +556,41 @@ int solve_jobs(int32_t n, const int32_t* pred_ptr, const int32_t* pred_idx, cons
     const int64_t max_rounds = o.max_rounds > 0 ? o.max_rounds : (int64_t)n + 2;
     JCtrl h;
     memset(&h, 0, sizeof(h));
-    int64_t r = 1;
+    // every launch runs at least one level or ends the sweep (a level past
+    // the limit sets over)
+    const int64_t max_launches = max_rounds + 2;
+    int64_t k = 0;
     int batch = 8;
+    // the level launches the last sweep of the same arrays needed: the first
+    // batch is sized from it, so a repeated solve enqueues few launches past
+    // its end (each costs a few microseconds); outputs do not depend on it
+    const JobsKey key((const void*)pred_ptr, (const void*)succ_ptr, n, E, a.narrow);
+    {
+        std::lock_guard<std::mutex> lk(g_jmu);
+        auto it = g_jhist.find(key);
+        if (it != g_jhist.end()) batch = std::max(2, it->second + 1);
+    }
     int status = LLP_OK;
-    for (;;) {
-        for (int i = 0; i < batch && r <= max_rounds; ++i, ++r)
-            hipLaunchKernelGGL(k_jobs_level, dim3(a.nseg), dim3(JB), 0, st, a, (int)r);
+    if (o.abort_host && *o.abort_host) status = LLP_E_ABORTED;   // set before the solve: no launch
+    for (; status == LLP_OK;) {
+        for (int i = 0; i < batch && k < max_launches; ++i, ++k)
+            hipLaunchKernelGGL(k_jobs_level, dim3(a.nseg), dim3(JB), 0, st, a, (int)k);
         LLP_HIP(hipGetLastError());
         s = readback(st, a.ctrl, &h, sizeof(h));
         if (s) return s;
-        if (h.status || h.done) break;
+        if (h.status) break;
+        if (h.done) {
+            if (h.over) status = LLP_E_NOT_CONVERGED;
+            break;
+        }
         if (o.abort_host && *o.abort_host) { status = LLP_E_ABORTED; break; }
-        if (r > max_rounds) { status = LLP_E_NOT_CONVERGED; break; }
+        if (k >= max_launches) { status = LLP_E_NOT_CONVERGED; break; }
         if (batch < 64) batch *= 2;
+    }
+    if (status == LLP_OK && h.status == 0 && h.done && !h.over) {
+        std::lock_guard<std::mutex> lk(g_jmu);
+        if (g_jhist.size() >= 256) g_jhist.clear();
+        g_jhist[key] = h.end_k + 1;
     }
     if (status == LLP_OK && h.status == 0) hipLaunchKernelGGL(k_jobs_final, dim3(grid1(n)), dim3(256), 0, st, a);
     LLP_HIP(hipGetLastError());

@@ -215,20 +215,24 @@ def diamond_dag(head=50, width=10000, tail=50):
 
 
 def job_cases():
-    """The readiness sweep, one launch per level: one job; a 300-job chain
-    (300 levels, one job each, most list segments empty); a random DAG; a
-    chain under a round limit it passes; a cycle behind a chain; a
-    completion time beyond int32; narrow, wide and narrow levels in turn."""
-    report_jobs("one", np.array([0, 0], np.int32), np.zeros(0, np.int32), np.array([5], np.int32))
-    report_jobs("chain", *chain_dag(300, 3))
+    """The readiness sweep: one job; a 300-job chain (300 levels, one job
+    each, most list segments empty); a random DAG; a chain under a round
+    limit it passes; a cycle behind a chain; a completion time beyond int32;
+    narrow, wide and narrow levels in turn.  Each with the narrow levels run
+    by one workgroup (the default), and with one launch per level (suffix
+    -l, chunk -1)."""
     pp, pi, d = llpgen.job_dag(3000, 4.0, 1, 1000, seed=9)
-    report_jobs("dag", pp, pi, d)
-    report_jobs("limit", *chain_dag(100), max_rounds=50)
-    pp, pi, d = chain_dag(40)
-    pp[0:3], pi = np.array([0, 1, 2], np.int32), np.concatenate([[2], pi[1:]]).astype(np.int32)
-    report_jobs("cycle", pp, pi, d)
-    report_jobs("overflow", *chain_dag(20, 1 << 28))
-    report_jobs("diamond", *diamond_dag())
+    cyc = chain_dag(40)
+    cyc[0][0:3] = np.array([0, 1, 2], np.int32)
+    cyc = (cyc[0], np.concatenate([[2], cyc[1][1:]]).astype(np.int32), cyc[2])
+    for suf, kw in (("", {}), ("-l", dict(chunk=-1))):
+        report_jobs("one" + suf, np.array([0, 0], np.int32), np.zeros(0, np.int32), np.array([5], np.int32), **kw)
+        report_jobs("chain" + suf, *chain_dag(300, 3), **kw)
+        report_jobs("dag" + suf, pp, pi, d, **kw)
+        report_jobs("limit" + suf, *chain_dag(100), max_rounds=50, **kw)
+        report_jobs("cycle" + suf, *cyc, **kw)
+        report_jobs("overflow" + suf, *chain_dag(20, 1 << 28), **kw)
+        report_jobs("diamond" + suf, *diamond_dag(), **kw)
 
 
 if __name__ == "__main__":

@@ -118,6 +118,7 @@ def test_sm_not_converged():
 # ---------------------------------------------------------------- jobs
 JOB_SCHEDS = [
     dict(),                                                        # readiness counters
+    dict(chunk=-1),                                                # the same, one launch per level
     dict(pull=True),                                               # pull, worklists
     dict(pull=True, sched=llp.SCHED_FIXED, flags=llp.DENSE),
     dict(pull=True, sched=llp.SCHED_FIXED, flags=llp.PUSH),
@@ -145,7 +146,7 @@ def test_jobs_all_schedules(n, seed, kw):
     assert np.array_equal(run_jobs(pp, pi, d, **kw), want)
 
 
-@pytest.mark.parametrize("kw", JOB_SCHEDS[:3], ids=job_ids)
+@pytest.mark.parametrize("kw", JOB_SCHEDS[:4], ids=job_ids)
 def test_jobs_full_size(kw):
     """2^20 jobs, in-degree min(Poisson(8), j) over lower ids, durations U[1,1000] (seed 4)."""
     pp, pi, d = llpgen.job_dag(1 << 20, seed=4)
@@ -153,7 +154,7 @@ def test_jobs_full_size(kw):
     st = llp.Stats()
     got = run_jobs(pp, pi, d, stats=st, **kw)
     assert np.array_equal(got, want)
-    if not kw:
+    if not kw.get("pull"):
         # every job with successors is listed once when fixed; every arc is read once
         sp, _ = llpgen.job_succ(pp, pi)
         assert st.advances == int((np.diff(sp) > 0).sum()) and st.edges_inspected == pi.shape[0]
@@ -166,26 +167,52 @@ def test_jobs_chain_and_isolated():
     pi = np.arange(0, n - 1, dtype=np.int32)
     d = llpgen.uniform_ints(n, 0, 1000, seed=8).astype(np.int32)
     want = oracle.jobs(pp, pi, d)
-    for kw in JOB_SCHEDS[:2]:
+    for kw in JOB_SCHEDS[:3]:
         assert np.array_equal(run_jobs(pp, pi, d, **kw), want), kw
     z = np.zeros(5, np.int32)
     assert run_jobs(np.zeros(6, np.int32), np.zeros(0, np.int32), z + 3).tolist() == [0] * 5
 
 
-def test_jobs_long_chain_and_round_limit():
-    # 9000 levels, one job each: launch batches up to their largest size, most list segments empty
+@pytest.mark.parametrize("kw", JOB_SCHEDS[:2], ids=job_ids)
+def test_jobs_long_chain_and_round_limit(kw):
+    # 9000 levels, one job each: launch batches up to their largest size, most
+    # list segments empty; by default 64 levels per launch in one workgroup
     n = 9000
     pp = np.concatenate([[0, 0], np.arange(1, n, dtype=np.int32)]).astype(np.int32)
     pi = np.arange(0, n - 1, dtype=np.int32)
     d = llpgen.uniform_ints(n, 0, 100, seed=9).astype(np.int32)
     want = oracle.jobs(pp, pi, d)
     st = llp.Stats()
-    assert np.array_equal(run_jobs(pp, pi, d, stats=st), want)
+    assert np.array_equal(run_jobs(pp, pi, d, stats=st, **kw), want)
     assert st.rounds == n - 1
     # a round limit below the depth ends the sweep with LLP_E_NOT_CONVERGED
+    st = llp.Stats()
     with pytest.raises(llp.LLPError) as e:
-        run_jobs(pp, pi, d, max_rounds=100)
+        run_jobs(pp, pi, d, max_rounds=100, stats=st, **kw)
     assert e.value.status == llp.E_NOT_CONVERGED
+
+
+def test_jobs_history_batches_on_reused_arrays():
+    """The first batch of level launches is sized from the last sweep of the
+    same arrays: a 3000-level chain and a two-level star with the same array
+    shapes, written in turn into the same device tensors, each solved against
+    the oracle (a stale history only changes how many launches are enqueued)."""
+    n = 3000
+    pp = np.concatenate([[0, 0], np.arange(1, n, dtype=np.int32)]).astype(np.int32)
+    chain = np.arange(0, n - 1, dtype=np.int32)
+    star = np.zeros(n - 1, np.int32)
+    d = llpgen.uniform_ints(n, 0, 1000, seed=10).astype(np.int32)
+    dev = [torch.from_numpy(x).cuda() for x in (pp, chain, d) + llpgen.job_succ(pp, chain)]
+    for pi in (chain, chain, star, chain, star):
+        sp, si = llpgen.job_succ(pp, pi)
+        dev[1].copy_(torch.from_numpy(pi))
+        dev[3].copy_(torch.from_numpy(sp))
+        dev[4].copy_(torch.from_numpy(si))
+        st = llp.Stats()
+        got = llp.jobs(*dev, stats=st)
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy(), oracle.jobs(pp, pi, d))
+        assert st.rounds == (n - 1 if pi is chain else 1)
 
 
 def cyclic_jobs():

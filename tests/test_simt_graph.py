@@ -87,15 +87,20 @@ def test_tail_rounds_and_local_queues(simt_lib):
 
 
 def test_jobs_levels(simt_lib):
-    """The readiness sweep (one launch per level): one job, a 300-level
+    """The readiness sweep, with its narrow levels run by one workgroup in
+    LDS and with one launch per level (suffix -l): one job, a 300-level
     chain, a random DAG, a round limit it runs past, a cycle, a completion
-    time beyond int32, and narrow levels around two of 10000 arcs; statuses
-    and start times against the oracle."""
+    time beyond int32, and narrow levels around two of 10000 arcs; statuses,
+    rounds and start times against the oracle."""
     by = {r["case"]: r for r in run_cases("jobs", 16)}
-    assert set(by) == {"one", "chain", "dag", "limit", "cycle", "overflow", "diamond"}
-    for name in ("one", "chain", "dag", "diamond"):
-        assert by[name]["status"] == 0 and by[name]["equal"], by[name]
-    assert by["chain"]["rounds"] == 299 and by["one"]["rounds"] == 0 and by["diamond"]["rounds"] == 101
-    assert by["limit"]["status"] == 5 and by["limit"]["rounds"] == 50       # LLP_E_NOT_CONVERGED
-    assert by["cycle"]["status"] == 8 and by["cycle"]["oracle_error"]        # LLP_E_CYCLE
-    assert by["overflow"]["status"] == 4 and by["overflow"]["oracle_error"]  # LLP_E_OVERFLOW
+    names = {"one", "chain", "dag", "limit", "cycle", "overflow", "diamond"}
+    assert set(by) == names | {x + "-l" for x in names}
+    for suf in ("", "-l"):
+        for name in ("one", "chain", "dag", "diamond"):
+            assert by[name + suf]["status"] == 0 and by[name + suf]["equal"], by[name + suf]
+        assert by["chain" + suf]["rounds"] == 299 and by["one" + suf]["rounds"] == 0
+        assert by["diamond" + suf]["rounds"] == 101
+        assert by["dag" + suf]["rounds"] == by["dag"]["rounds"]
+        assert by["limit" + suf]["status"] == 5 and by["limit" + suf]["rounds"] == 50       # LLP_E_NOT_CONVERGED
+        assert by["cycle" + suf]["status"] == 8 and by["cycle" + suf]["oracle_error"]        # LLP_E_CYCLE
+        assert by["overflow" + suf]["status"] == 4 and by["overflow" + suf]["oracle_error"]  # LLP_E_OVERFLOW
