@@ -1097,7 +1097,7 @@ __device__ void bm_prepare(const GArgs& a, int r, int cap, const ListRef& in, co
 // BM: a bounded BFS dense round prepares the bitmap here and is evaluated by
 // the next launch.
 template <bool LQ, bool BM>
-__device__ __forceinline__ int pre_phase(const GArgs& a, int r, int k, GShared& sh) {
+__device__ __forceinline__ int pre_phase(const GArgs& a, int r, int k, GShared& sh, const SegRegs& sin) {
     const ListRef in = cl_of(a, r - 1);
     const ListRef out = cl_of(a, r);
     // the learned schedule's inputs besides the list totals (its weights and
@@ -1108,7 +1108,7 @@ __device__ __forceinline__ int pre_phase(const GArgs& a, int r, int k, GShared& 
         wl = mlp_load(a.sp.mlp);
         hprev = a.ctrl->hist[(r + 1) & 1];
     }
-    load_segments(in.seg, a.nseg, sh.cnt, sh.epre, sh.tmp, &sh.tot_edges, &sh.tot_count);
+    seg_scan(sin, a.nseg, sh.cnt, sh.epre, sh.tmp, &sh.tot_edges, &sh.tot_count);   // totals of CL[r-1]
     const int force_dense = (r == 1 && a.warm_dense);
     if (blockIdx.x == 0 && threadIdx.x == 0 && a.trace && r >= 2 && r - 2 < a.trace_cap) {
         // entries the previous round's delta filter carried
@@ -1384,16 +1384,21 @@ __device__ __forceinline__ void main_phase(const GArgs& a, int r, int verify, in
 template <bool LQ, bool BM>
 __global__ void __launch_bounds__(GB, 4) k_graph_step(GArgs a, int k) {
     __shared__ GShared sh;
+    // one round trip for the launch's control words and the totals of both
+    // changed lists (the round's parity picks one)
+    SegRegs s0, s1;
+    seg_fetch(a.cl0.seg, a.nseg, s0);
+    seg_fetch(a.cl1.seg, a.nseg, s1);
+    const int ph = a.ctrl->step_phase[k & 1];
+    const int rr = a.ctrl->step_round[k & 1];
     if (ld_relaxed(&a.ctrl->stop[k & 1]) || ld_relaxed(&a.ctrl->status)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) st_relaxed(&a.ctrl->stop[(k + 1) & 1], 1);
         return;
     }
-    const int ph = a.ctrl->step_phase[k & 1];
-    const int rr = a.ctrl->step_round[k & 1];
     int r = rr, code;
     if (ph == 0) {
         r = rr + 1;
-        code = pre_phase<LQ, BM>(a, r, k, sh);
+        code = pre_phase<LQ, BM>(a, r, k, sh, (rr & 1) ? s1 : s0);   // CL[r-1] = CL[rr]
         if (code < 0) return;
     } else {
         code = a.ctrl->mode;

@@ -83,11 +83,26 @@ struct SegView {
     int total_count;
 };
 
-// Block-wide scan of the packed segment totals into LDS arrays.
-// lds_cnt[nseg], lds_epre[nseg+1] must be __shared__ buffers.
+// This thread's packed segment totals (segments t * per .. t * per + per - 1,
+// per = ceil(nseg / blockDim) <= 8), fetched ahead of the scan so that a
+// kernel can issue them together with its other first loads.
+struct SegRegs {
+    unsigned long long x[8];
+};
 template <bool COH = false>
-__device__ inline void load_segments(const unsigned long long* seg, int nseg, int* lds_cnt, int* lds_epre,
-                                     int* lds_tmp /* >= blockDim/64 + 1 ints */, int* tot_edges, int* tot_count) {
+__device__ inline void seg_fetch(const unsigned long long* seg, int nseg, SegRegs& s) {
+    const int per = (nseg + blockDim.x - 1) / blockDim.x;
+    const int b = threadIdx.x * per, e = min(b + per, nseg);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s.x[k] = (k < per && b + k < e) ? ld_u64<COH>(seg + b + k) : 0ull;
+}
+
+// Block-wide scan of fetched segment totals into LDS arrays.
+// lds_cnt[nseg], lds_epre[nseg+1] must be __shared__ buffers.  (A template,
+// like every helper here that declares its own LDS.)
+template <int = 0>
+__device__ inline void seg_scan(const SegRegs& s, int nseg, int* lds_cnt, int* lds_epre,
+                                int* lds_tmp /* >= blockDim/64 + 1 ints */, int* tot_edges, int* tot_count) {
     const int t = threadIdx.x, nt = blockDim.x;
     const int per = (nseg + nt - 1) / nt;   // <= 8 (nseg <= 2048, >= 256 threads)
     const int b = t * per, e = min(b + per, nseg);
@@ -98,7 +113,7 @@ __device__ inline void load_segments(const unsigned long long* seg, int nseg, in
         const int i = b + k;
         eds[k] = 0;
         if (k < per && i < e) {
-            unsigned long long x = ld_u64<COH>(seg + i);
+            const unsigned long long x = s.x[k];
             int c = (int)(x & 0xffffffffull), ed = (int)(x >> 32);
             lds_cnt[i] = c;
             eds[k] = ed;
@@ -138,6 +153,15 @@ __device__ inline void load_segments(const unsigned long long* seg, int nseg, in
     *tot_count = (int)ctot;
     (void)lds_tmp;
     __syncthreads();
+}
+
+// Fetch and scan in one step.
+template <bool COH = false>
+__device__ inline void load_segments(const unsigned long long* seg, int nseg, int* lds_cnt, int* lds_epre,
+                                     int* lds_tmp /* >= blockDim/64 + 1 ints */, int* tot_edges, int* tot_count) {
+    SegRegs s;
+    seg_fetch<COH>(seg, nseg, s);
+    seg_scan(s, nseg, lds_cnt, lds_epre, lds_tmp, tot_edges, tot_count);
 }
 
 // ---------------------------------------------------------------- sources
