@@ -669,7 +669,7 @@ __device__ __forceinline__ bool lq_put(GShared& sh, bool want, int x, int ob, in
 // below the bucket's ceiling, as the round would have pushed them.
 constexpr int CDEG = 2;
 constexpr int CDEPTH = 32;
-constexpr int CONT_EDGES = 1 << 20;   // rounds with at most this many arcs to push
+constexpr int CONT_EDGES = 1 << 22;   // rounds with at most this many arcs to push
 
 template <bool COH>
 __device__ void push_continue(const GArgs& a, int r, int cv, int cg, int cob, int cod, long long hi, const ListRef& out,
