@@ -217,7 +217,7 @@ __global__ void k_graph_validate(GArgs a) {
 // are evaluated by one wave, longer rows are split between waves by arc range.
 constexpr int DBLK = 512;     // arcs per block: 8 per lane
 constexpr int DSHORT = 64;    // longest row reduced by a single lane
-constexpr int DLONG = 4096;   // longest row evaluated by a single wave
+constexpr int DLONG = 1024;   // longest row evaluated by a single wave
 
 struct GShared {
     int cnt[MAX_SEG];
@@ -628,7 +628,7 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
 // distance >= hi is carried into CL[r] (by the block where it starts) and
 // none of its arcs is pushed; the test is monotone (distances only fall), so
 // an entry pushed in part is never carried.
-constexpr int PJ = 4;
+constexpr int PJ = 2;
 constexpr int PBLK = 64 * PJ;
 
 // Local queue of a bucketed push round (the per-worker work bag of the
