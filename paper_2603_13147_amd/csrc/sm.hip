@@ -237,6 +237,7 @@ __global__ void k_sm_chain(SArgs a, int r) {
 // starts men t, t + 1024, ... in turn and carries displaced men as above.
 constexpr int SM_LDS_MAX = 12288;   // 12 B of LDS per man: 144 KB
 constexpr int SM_COMBO = 64;        // list positions per man held as (woman, rank) pairs
+constexpr int SM_LDS_LOOKAHEAD = 6;   // women examined per round trip of a chain in k_sm_lds
 constexpr int SM_LDS_THREADS = 1024;
 
 // The i-th woman w on m's list and her rank of m, as w | rank << 16.
@@ -279,19 +280,19 @@ __global__ void __launch_bounds__(SM_LDS_THREADS) k_sm_lds(SArgs a) {
                 infeasible = true;
                 break;
             }
-            const int la = min(SM_LOOKAHEAD, n - g);
-            int wv[SM_LOOKAHEAD], cw[SM_LOOKAHEAD];
-            unsigned long long kv[SM_LOOKAHEAD], bv[SM_LOOKAHEAD];
-            if (g + SM_LOOKAHEAD <= SM_COMBO) {   // the whole look-ahead window is in the table
+            const int la = min(SM_LDS_LOOKAHEAD, n - g);
+            int wv[SM_LDS_LOOKAHEAD], cw[SM_LDS_LOOKAHEAD];
+            unsigned long long kv[SM_LDS_LOOKAHEAD], bv[SM_LDS_LOOKAHEAD];
+            if (g + SM_LDS_LOOKAHEAD <= SM_COMBO) {   // the whole look-ahead window is in the table
 #pragma unroll
-                for (int i = 0; i < SM_LOOKAHEAD; ++i) cw[i] = i < la ? a.combo[(long long)m * SM_COMBO + g + i] : 0;
+                for (int i = 0; i < SM_LDS_LOOKAHEAD; ++i) cw[i] = i < la ? a.combo[(long long)m * SM_COMBO + g + i] : 0;
             } else {
 #pragma unroll
-                for (int i = 0; i < SM_LOOKAHEAD; ++i)
+                for (int i = 0; i < SM_LDS_LOOKAHEAD; ++i)
                     cw[i] = i >= la ? 0 : g + i < SM_COMBO ? a.combo[(long long)m * SM_COMBO + g + i] : sm_pair(a, m, g + i);
             }
 #pragma unroll
-            for (int i = 0; i < SM_LOOKAHEAD; ++i) {
+            for (int i = 0; i < SM_LDS_LOOKAHEAD; ++i) {
                 wv[i] = cw[i] & 0xffff;   // < n: sm_pair guarded it
                 kv[i] = ~0ull;
                 bv[i] = 0ull;
@@ -302,7 +303,7 @@ __global__ void __launch_bounds__(SM_LDS_THREADS) k_sm_lds(SArgs a) {
             }
             int skip = 0;
 #pragma unroll
-            for (int i = 0; i < SM_LOOKAHEAD; ++i)
+            for (int i = 0; i < SM_LDS_LOOKAHEAD; ++i)
                 if (skip == i && i < la && bv[i] < kv[i]) skip = i + 1;
             if (skip == la) {
                 g += la;
@@ -314,7 +315,7 @@ __global__ void __launch_bounds__(SM_LDS_THREADS) k_sm_lds(SArgs a) {
             int w = 0;
             unsigned long long key = 0;
 #pragma unroll
-            for (int i = 0; i < SM_LOOKAHEAD; ++i)
+            for (int i = 0; i < SM_LDS_LOOKAHEAD; ++i)
                 if (i == skip) {
                     w = wv[i];
                     key = kv[i];
