@@ -201,6 +201,28 @@ def test_not_converged_and_warm_start():
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("kw", [dict(sched=llp.SCHED_HYBRID), dict(sched=llp.SCHED_FIXED, flags=llp.DENSE)],
+                         ids=["hybrid", "dense"])
+def test_bfs_warm_start(kw):
+    """BFS resumed from a partial state (a sweep stopped by the round limit):
+    the sweep takes the kernel without the bitmap (a warm first dense round
+    has no bound) and reaches the oracle's levels."""
+    g = llpgen.rmat_graph(15, seed=44)
+    s = llpgen.max_outdeg_source(g)
+    _, dg = dev_graph(g)
+    want = oracle.bfs(g.n, g.src, g.dst, s, bag=True)
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    with pytest.raises(llp.LLPError) as e:
+        llp.bfs(dg, s, out=out, max_rounds=2, **kw)
+    assert e.value.status == llp.E_NOT_CONVERGED
+    part = out.cpu().numpy()
+    assert np.all(part.astype(np.int64) >= want) and part[s] == 0
+    st = llp.Stats()
+    got = run(llp.bfs, dg, s, warm_start=out.clone(), stats=st, **kw)
+    assert np.array_equal(got, want)
+    assert st.bitmap_rounds == 0
+
+
 def test_verify_and_stats_and_trace():
     g = llpgen.uniform_graph(4096, 32768, 1, 100, seed=2)
     _, dg = dev_graph(g)
