@@ -74,3 +74,20 @@ def test_kernel_bytes_prices_the_bitmap():
     # reads the n states and writes the bitmap once per round
     assert main2 == 4 * 100 + 4 * 40 + 16 * 10 + 2 * (n // 8)
     assert pre2 == 16 * 7 + 8 * 5 + 8 * 3 + 2 * 4 * n + 2 * (n // 8)
+
+
+def test_cli_refuses_several_gpus_and_needs_one():
+    """--gpus above 1 exits with a message (the sweep does not shard); without
+    a visible GPU the bench prints an error line instead of a measurement."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert json.loads(r.stdout.strip().splitlines()[-1])["n_gpus"] == 2
+    import torch
+    if not torch.cuda.is_available():
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "1", "--warmup", "0"],
+                           capture_output=True, text=True, timeout=300)
+        assert r.returncode == 1
+        assert "error" in json.loads(r.stdout.strip().splitlines()[-1])
