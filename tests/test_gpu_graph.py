@@ -270,6 +270,27 @@ def test_dense_bound_counts():
     assert sb.states_gathered == 0
 
 
+@pytest.mark.parametrize("wlo,whi", [(1, 1), (1, 255), (200, 300), (1, 1000000)])
+@pytest.mark.parametrize("kw", [dict(sched=llp.SCHED_FIXED, flags=llp.DENSE), dict(sched=llp.SCHED_HYBRID)],
+                         ids=["dense", "hybrid"])
+def test_sssp_weight_ranges(wlo, whi, kw):
+    """SSSP on a ragged R-MAT graph with unit, narrow-band, the bench's and
+    very wide (up to 10^6) weights, under dense rounds (and their arc bound
+    dmin + w < d) and the hybrid: the oracle's distances, and the dense
+    rounds gather some but not more states than arcs they read."""
+    e = llpgen.rmat_graph(13, seed=61)
+    rng = np.random.default_rng(61)
+    g = llpgen.EdgeList(e.n, e.src, e.dst, rng.integers(wlo, whi + 1, size=e.m).astype(np.int32))
+    s = llpgen.max_outdeg_source(g)
+    _, dg = dev_graph(g)
+    st = llp.Stats()
+    got = run(llp.sssp, dg, s, stats=st, **kw)
+    assert np.array_equal(got, oracle.sssp(g.n, g.src, g.dst, g.w, s, bag=True))
+    assert st.bitmap_rounds == 0
+    if kw.get("flags") == llp.DENSE:
+        assert 0 < st.states_gathered <= st.edges_inspected
+
+
 def test_bfs_bitmap_round_carries():
     """A BFS dense round with the bitmap right after a push round whose
     chains reached past the next level: the list entries above the round's
