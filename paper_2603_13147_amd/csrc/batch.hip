@@ -43,6 +43,7 @@ constexpr int KN_MAX_W = 16383;
 // built for (16384 cells per workgroup keeps the register budget).
 constexpr int ch_max_block(int ch) { return 16384 / ch > 1024 ? 1024 : 16384 / ch; }
 constexpr int SS_MAX_N = 8192;
+constexpr size_t BATCH_STATIC_LDS = 64;   // bytes of k_batch's static LDS (claim word, flags), rounded up
 
 struct BCtrl {
     int head;          // queue: next unclaimed instance
@@ -531,9 +532,11 @@ static int batch_plan(int32_t count, const llp_instance* desc, const llp_opts& o
     const size_t ss = (size_t)p->ss_n * 4 + 2 * (size_t)((p->ss_n + 31) / 32) * 4 + (size_t)(p->ss_n + 1) * 4;
     size_t need1 = row > ss ? row : ss;
     size_t need2 = 2 * row > ss ? 2 * row : ss;
-    p->kn_dbuf = need2 <= lds_limit();
+    // k_batch's own LDS (the claim word and the solver flags) comes first
+    const size_t lim = lds_limit() - BATCH_STATIC_LDS;
+    p->kn_dbuf = need2 <= lim;
     p->lds = p->kn_dbuf ? need2 : need1;
-    if (p->lds > lds_limit()) return fail(LLP_E_ARG, "instances need %zu bytes of LDS", p->lds);
+    if (p->lds > lim) return fail(LLP_E_ARG, "instances need %zu bytes of LDS", p->lds);
     return LLP_OK;
 }
 
