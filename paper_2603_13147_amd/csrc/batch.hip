@@ -510,17 +510,25 @@ static int batch_plan(int32_t count, const llp_instance* desc, const llp_opts& o
     if (h.max_w > KN_MAX_W) return fail(LLP_E_ARG, "a knapsack instance has W = %d > %d", h.max_w, KN_MAX_W);
     if (h.max_n > SS_MAX_N) return fail(LLP_E_ARG, "an SSSP instance has n = %d > %d", h.max_n, SS_MAX_N);
     int block = o.block, chunk = o.chunk;
+    bool tuned_block = false;
     if (block <= 0 || chunk <= 0) {
         // the autotuner's record for this batch's size class (or the nearest)
         int tb = 0, tc = 0;
         if (tune_lookup(LLP_KIND_BATCH, count, &tb, &tc)) {
-            if (block <= 0) block = tb;
+            if (block <= 0) {
+                block = tb;
+                tuned_block = true;
+            }
             if (chunk <= 0) chunk = tc;
         }
     }
     if (block <= 0) block = 512;   // the autotuner's usual choice on the mixed batch
     if (chunk <= 0) chunk = 1;
     if (block % 64 != 0 || block > 1024) return fail(LLP_E_ARG, "block must be a multiple of 64 up to 1024");
+    // a record is keyed by the instance count only: when its workgroup is too
+    // small for this batch's widest knapsack row, 512 threads hold any W up
+    // to KN_MAX_W
+    if (tuned_block && !pick_ch(h.max_w, block)) block = 512;
     p->block = block;
     p->chunk = chunk;
     p->ch = pick_ch(h.max_w, block);

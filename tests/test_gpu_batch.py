@@ -111,6 +111,61 @@ def test_batch_edge_instances():
     assert got[3].tolist() == [0, 4, I32] and got[4].tolist() == [I32, I32, 0]
 
 
+def test_batch_largest_instances():
+    """The largest instances a batch takes: an SSSP graph of n = 8192 (state,
+    two frontier bitmaps and row offsets in LDS) and a knapsack of W = 16383,
+    mixed with small ones; the launch's LDS (with the batch kernel's own
+    static words) fits one workgroup, and the results equal the oracle's.  One
+    vertex more is refused with LLP_E_ARG before anything is launched."""
+    rng = np.random.default_rng(12)
+    g = llpgen.uniform_graph(8192, 8 * 8192, 1, 100, seed=12)
+    wt = rng.integers(1, 4096, size=40).astype(np.int32)
+    val = rng.integers(1, 1000, size=40).astype(np.int32)
+    items = [("sssp", g, 0), ("knapsack", wt, val, 16383)] + small_batch(seed=12, nk=3, ns=3)
+    b = llp.Batch(items).solve()
+    torch.cuda.synchronize()
+    check_batch(items, b)
+    big = llpgen.uniform_graph(8193, 8 * 8193, 1, 100, seed=13)
+    with pytest.raises(llp.LLPError) as e:
+        llp.Batch([("sssp", big, 0)]).solve()
+    assert e.value.status == llp.E_ARG
+
+
+def test_batch_tuned_block_too_small_for_widest_row(tmp_path):
+    """A tuned record is keyed by the instance count only: a record of 256
+    threads (at most 8192 knapsack cells per workgroup) for this batch's size
+    class must not make a batch with W = 16383 fail; the plan takes 512
+    threads instead, and the results equal the oracle's."""
+    import json
+    rng = np.random.default_rng(14)
+    wt = rng.integers(1, 4096, size=24).astype(np.int32)
+    val = rng.integers(1, 1000, size=24).astype(np.int32)
+    items = [("knapsack", wt, val, 16383)] + small_batch(seed=14, nk=3, ns=4)
+    probe = llp.Batch(small_batch(seed=15, nk=4, ns=4))   # the same count, small rows
+    assert probe.count == len(items)
+    probe.autotune()
+    path = tmp_path / "cache.json"
+    llp.autotune_save(str(path))
+    doc = json.loads(path.read_text())
+    cls = len(items).bit_length() - 1
+    ents = [e for e in doc["entries"] if e["kind"] == "batch" and e["size_class"] == cls]
+    assert ents, doc
+    for e in ents:
+        e["block"], e["chunk"] = 256, 1
+    path.write_text(json.dumps({"llp_autotune": 1, "entries": ents}))
+    llp.autotune_load(str(path))
+    try:
+        assert llp.autotune_lookup(llp.KIND_BATCH, len(items)) == (256, 1)
+        b = llp.Batch(items).solve()
+        torch.cuda.synchronize()
+        check_batch(items, b)
+    finally:
+        for e in ents:
+            e["block"], e["chunk"] = 512, 1
+        path.write_text(json.dumps({"llp_autotune": 1, "entries": ents}))
+        llp.autotune_load(str(path))
+
+
 def test_batch_rejects_out_of_range_instance():
     items = small_batch(seed=3, nk=4, ns=4)
     b = llp.Batch(items)
