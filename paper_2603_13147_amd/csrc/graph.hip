@@ -509,8 +509,9 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
         const int thr = l < k ? arc_bound(R.g, dlo) : 0x7fffffff;
         const bool lim = ballot(thr != 0x7fffffff) != 0ull;
         // the row of each arc position, when some row of the block is final
-        // (positions skip its arcs) or has a bound: row l writes l + 1 at its
-        // first position and a max-scan over the positions fills the rest (cb
+        // (positions skip its arcs) or has a bound: row l writes l at its
+        // first position over a fill of -1, and a max-scan over the positions
+        // fills the rest (position 0 starts the first row with arcs; cb
         // holds this table until the candidates are written); per row: rt its
         // arc bound, ra its first arc, rc its first position
         int* rt = cb + DBLK;
@@ -524,22 +525,22 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
                 rc[l] = cs;
             }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) cb[8 * l + j] = 0;
+            for (int j = 0; j < 8; ++j) cb[8 * l + j] = -1;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (l < k && len > 0) cb[cs] = l + 1;
+            if (l < k && len > 0) cb[cs] = l;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            int q[8], run = 0;
+            int q[8], run = -1;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 run = max(run, cb[8 * l + j]);
                 q[j] = run;
             }
             int before = __shfl_up(wave_incl_max(run), 1, LLP_WAVE);
-            if (l == 0) before = 0;
+            if (l == 0) before = -1;
 #pragma unroll
             for (int j = 0; j < 8; ++j) cb[8 * l + j] = max(before, q[j]);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -558,7 +559,7 @@ __device__ void dense_wave(const GArgs& a, int r, int wb, int we, const ListRef&
             t[j] = 0x7fffffff;
             int i = P0 + p;
             if (table && act[j]) {
-                const int o = cb[p] - 1;
+                const int o = cb[p];
                 t[j] = rt[o];
                 if (fin) i = ra[o] + (p - rc[o]);   // positions skip the final rows' arcs
             }
