@@ -91,3 +91,27 @@ def test_cli_refuses_several_gpus_and_needs_one():
                            capture_output=True, text=True, timeout=300)
         assert r.returncode == 1
         assert "error" in json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def test_committed_traffic_follows_the_kernel_sources(tmp_path):
+    """The bench reports the committed counter traffic of a phase only while
+    the step kernel's sources hash as they did when the counters were taken:
+    the committed summary matches the tree as it is, and a one-byte change to
+    a kernel source (in a copy of the tree) turns the figure into None."""
+    import shutil
+    b = load_bench()
+    rec = json.load(open(os.path.join(ROOT, "profiles", "k_graph_step_rmat22_hybrid.traffic.json")))
+    assert b.committed_traffic("main") == rec["phases"]["main"]["traffic_bytes_per_launch"]
+    assert b.committed_traffic("pre") == rec["phases"]["pre"]["traffic_bytes_per_launch"]
+    assert b.committed_traffic("tail") is None
+    csrc = tmp_path / "paper_2603_13147_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    for f in b.KERNEL_SOURCES:
+        shutil.copy(os.path.join(ROOT, "paper_2603_13147_amd", "csrc", f), csrc / f)
+    (tmp_path / "profiles").mkdir()
+    shutil.copy(os.path.join(ROOT, "profiles", "k_graph_step_rmat22_hybrid.traffic.json"), tmp_path / "profiles")
+    b.ROOT = str(tmp_path)
+    assert b.committed_traffic("main") == rec["phases"]["main"]["traffic_bytes_per_launch"]
+    with open(csrc / b.KERNEL_SOURCES[0], "ab") as f:
+        f.write(b"\n")
+    assert b.committed_traffic("main") is None
