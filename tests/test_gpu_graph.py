@@ -407,3 +407,25 @@ def test_trace_records_delta_rounds():
     assert rec["pending"].sum() > 0                      # some vertices waited for their bucket
     assert rec["out_count"].sum() > 0                    # pull rounds evaluated candidates
 
+
+
+def test_repeated_solves_equal_the_oracle():
+    """25 SSSP and 25 BFS solves of one R-MAT scale-18 graph under the hybrid
+    and the fixed dense schedules, alternating kinds on one shared workspace
+    and output buffer: every output equals the oracle's, so no run depends on
+    the order in which workgroups happen to run or on what an earlier solve
+    left in the workspace."""
+    g = llpgen.rmat_graph(18, seed=18)
+    s = llpgen.max_outdeg_source(g)
+    _, dg = dev_graph(g)
+    want = {llp.sssp: oracle.sssp(g.n, g.src, g.dst, g.w, s, bag=True),
+            llp.bfs: oracle.bfs(g.n, g.src, g.dst, s, bag=True)}
+    ws = llp.workspace(llp.KIND_SSSP, g.n, g.m)
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    for i in range(25):
+        for kw in (dict(sched=llp.SCHED_HYBRID), dict(sched=llp.SCHED_FIXED, flags=llp.DENSE)):
+            for fn in (llp.sssp, llp.bfs):
+                out.fill_(-5)
+                fn(dg, s, out=out, ws=ws, **kw)
+                torch.cuda.synchronize()
+                assert np.array_equal(out.cpu().numpy(), want[fn]), (i, kw, fn.__name__)
