@@ -254,3 +254,36 @@ def test_jobs_overflow_and_validation():
     with pytest.raises(llp.LLPError) as e:
         llp.jobs(pp, pi, d, sp, si, flags=llp.VALIDATE)
     assert e.value.status == llp.E_INPUT
+
+
+def test_jobs_repeated_solves_equal_the_oracle():
+    """30 readiness solves of one 2^18-job DAG (wide levels and runs of narrow
+    ones) in each form: narrow levels in one workgroup up to 1024 arcs, up to
+    256 arcs (more hand-overs between the forms), and one launch per level.
+    Every output equals the oracle's, whatever order the workgroups run in."""
+    pp, pi, d = llpgen.job_dag(1 << 18, seed=21)
+    sp, si = llpgen.job_succ(pp, pi)
+    want = oracle.jobs(pp, pi, d)
+    dev = [torch.from_numpy(x).cuda() for x in (pp, pi, d, sp, si)]
+    for i in range(30):
+        for kw in (dict(), dict(chunk=256), dict(chunk=-1)):
+            st = llp.Stats()
+            got = llp.jobs(*dev, stats=st, **kw)
+            torch.cuda.synchronize()
+            assert np.array_equal(got.cpu().numpy(), want), (i, kw)
+            assert st.rounds > 1
+
+
+def test_sm_repeated_solves_equal_the_oracle():
+    """20 solves of one n = 4096 instance in the single-workgroup chain form
+    and in the grid chain form, on device tensors reused across runs: the
+    chains interleave differently from run to run, but the man-optimal
+    matching is unique, and every run returns the oracle's."""
+    mpref, wrank = llpgen.sm_prefs(4096, seed=22)
+    want_w, want_p = oracle.stable_marriage(mpref, wrank)
+    mp, wr = torch.from_numpy(mpref).cuda(), torch.from_numpy(wrank).cuda()
+    for i in range(20):
+        for kw in (dict(), dict(chunk=4)):
+            w, p = run_sm(mp, wr, **kw)
+            assert np.array_equal(w, want_w), (i, kw)
+            assert np.array_equal(p, want_p), (i, kw)
