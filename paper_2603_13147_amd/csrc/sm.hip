@@ -86,11 +86,7 @@ __global__ void k_sm_init(SArgs a, const int* warm) {
         a.best[i] = SM_EMPTY;
         a.pend[i] = 1;
     }
-    if (tid == 0) {
-        SCtrl c;
-        memset(&c, 0, sizeof(c));
-        *a.ctrl = c;
-    }
+    if (tid == 0) memset(a.ctrl, 0, sizeof(SCtrl));
 }
 
 __device__ __forceinline__ int sm_warm(const SArgs& a, int m) {
