@@ -22,14 +22,24 @@ __device__ __forceinline__ int mbcnt(uint64_t mask) {
 
 __device__ __forceinline__ int shfl(int v, int src) { return __shfl(v, src, LLP_WAVE); }
 
+// Wave scans by DPP (all 64 lanes active): four row shifts give the
+// inclusive scan within each row of 16 lanes, then the last lane of row 0
+// is broadcast into row 1 and that of row 2 into row 3, and lane 31 (rows 0
+// and 1 complete) into rows 2 and 3.  A lane whose source lies outside its
+// row, or whose row the mask leaves out, takes the identity.  No lane
+// comparison or LDS crossbar trip is involved.
+constexpr int DPP_ROW_SHR = 0x110;     // + shift (1..15)
+constexpr int DPP_ROW_BCAST15 = 0x142;
+constexpr int DPP_ROW_BCAST31 = 0x143;
+
 // inclusive prefix sum over the wave
 __device__ __forceinline__ int wave_incl_sum(int x) {
-    const int l = lane();
-#pragma unroll
-    for (int d = 1; d < LLP_WAVE; d <<= 1) {
-        int y = __shfl_up(x, d, LLP_WAVE);
-        if (l >= d) x += y;
-    }
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_SHR + 1, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_SHR + 2, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_SHR + 4, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_SHR + 8, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_BCAST15, 0xa, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_ROW_BCAST31, 0xc, 0xf, false);
     return x;
 }
 
@@ -43,14 +53,15 @@ __device__ __forceinline__ long long wave_incl_sum64(long long x) {
     return x;
 }
 
-// inclusive max scan over the wave
+// inclusive max scan over the wave (same steps as wave_incl_sum)
 __device__ __forceinline__ int wave_incl_max(int x) {
-    const int l = lane();
-#pragma unroll
-    for (int d = 1; d < LLP_WAVE; d <<= 1) {
-        int y = __shfl_up(x, d, LLP_WAVE);
-        if (l >= d) x = max(x, y);
-    }
+    constexpr int lo = -2147483647 - 1;
+    x = max(x, __builtin_amdgcn_update_dpp(lo, x, DPP_ROW_SHR + 1, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(lo, x, DPP_ROW_SHR + 2, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(lo, x, DPP_ROW_SHR + 4, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(lo, x, DPP_ROW_SHR + 8, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(lo, x, DPP_ROW_BCAST15, 0xa, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(lo, x, DPP_ROW_BCAST31, 0xc, 0xf, false));
     return x;
 }
 

@@ -133,6 +133,32 @@ static inline unsigned simt_mbcnt_hi(unsigned m, unsigned acc) {
     if (l >= 32 && l < 63) mask = (1u << (l - 32)) - 1u;
     return acc + __builtin_popcount(m & mask);
 }
+// DPP row shifts and row broadcasts (the controls the sweep uses): the value
+// of the source lane, or old where the source lies outside the lane's row or
+// the lane's row or bank is masked off.  Every lane of the wave takes part.
+// (One call site for the shuffle and a select after it: a branch after the
+// call lets the compiler copy the call into each path, which the divergence
+// check would see as different sites.)
+__attribute__((noinline)) static int simt_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask,
+                                                     bool bound_ctrl) {
+    const int l = ::simt::lane_id(), row = l >> 4, bank = (l & 15) >> 2;
+    int from = -1;
+    if (ctrl > 0x110 && ctrl < 0x120) {
+        const int d = ctrl - 0x110;
+        if ((l & 15) >= d) from = l - d;
+    } else if (ctrl == 0x142) {
+        if (row >= 1) from = row * 16 - 1;
+    } else if (ctrl == 0x143) {
+        if (row >= 2) from = 31;
+    } else {
+        __builtin_trap();
+    }
+    const int v = __shfl(src, from < 0 ? l : from);
+    const bool on = ((row_mask >> row) & 1) && ((bank_mask >> bank) & 1);
+    const int off = bound_ctrl ? 0 : old;
+    return on ? (from < 0 ? off : v) : old;
+}
+#define __builtin_amdgcn_update_dpp(o, s, c, rm, bm, bc) simt_update_dpp((o), (s), (c), (rm), (bm), (bc))
 #define __builtin_amdgcn_mbcnt_lo(m, a) simt_mbcnt_lo((m), (a))
 #define __builtin_amdgcn_mbcnt_hi(m, a) simt_mbcnt_hi((m), (a))
 #define __builtin_amdgcn_fence(...) ((void)0)
