@@ -65,10 +65,10 @@ __device__ __forceinline__ int wave_incl_max(int x) {
     return x;
 }
 
+// maximum over the wave, in every lane: the DPP max scan, whose lane 63
+// holds the whole wave's maximum, then one shuffle from that lane
 __device__ __forceinline__ int wave_max(int x) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x = max(x, __shfl_xor(x, d, LLP_WAVE));
-    return x;
+    return __shfl(wave_incl_max(x), 63, LLP_WAVE);
 }
 
 __device__ __forceinline__ long long wave_sum64(long long x) {
