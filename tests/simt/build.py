@@ -6,6 +6,7 @@ infrastructure only: the product library is built by paper_2603_13147_amd/_build
 from __future__ import annotations
 
 import os
+import shutil
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -28,19 +29,25 @@ def build() -> str:
     os.makedirs(OUT, exist_ok=True)
     san = ["-fsanitize=address", "-fno-omit-frame-pointer"] if asan_runtime() else []
     flags = ["-std=c++17", "-O1", "-g", "-fPIC", "-I", HERE, "-Wno-unused-result", "-Wno-attributes", *san]
+    # objects and the unlinked library are private to this process, so test
+    # workers that build at the same time do not overwrite each other's files
+    # (the finished library replaces the old one in a single rename)
+    odir = os.path.join(OUT, f"obj-{os.getpid()}")
+    os.makedirs(odir, exist_ok=True)
     objs = []
     for src in SOURCES:
-        obj = os.path.join(OUT, os.path.basename(src) + ".o")
+        obj = os.path.join(odir, os.path.basename(src) + ".o")
         lang = ["-x", "c++"] if src.endswith(".hip") else []
         r = subprocess.run(["g++", *flags, *lang, "-c", src, "-o", obj], capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"g++ failed for {src}:\n{r.stderr}")
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = LIB + f".{os.getpid()}.tmp"
     r = subprocess.run(["g++", *san, "-shared", "-o", tmp, *objs], capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    shutil.rmtree(odir, ignore_errors=True)
     return LIB
 
 
